@@ -1,0 +1,126 @@
+/*
+ * libifgf — IFGF-accelerated N-Mueller boundary-integral operator on MI355X.
+ *
+ * Implements the hot path of Paul & Sideris, "Accelerated 3D Maxwell Integral
+ * Equation Solver using the Interpolated Factored Green Function Method"
+ * (arXiv 2408.02274): the Green's-function and Green's-gradient sums over
+ * Chebyshev-Nystrom surface points at two wavenumbers (Sec. III-E..III-I,
+ * eq. ifgf_sum_em), the near-field singular corrections (Sec. III-D, III-H),
+ * the N-Mueller operator built from them (Sec. II, eq. n_muller..t_delta) and
+ * GMRES on the resulting 4N x 4N system (Sec. III-A, eq. lin_system).
+ *
+ * Conventions for every entry point
+ *  - Status: 0 = IFGF_OK, < 0 error, > 0 warning.  On error the thread-local
+ *    message is available from ifgf_last_error().  No entry point aborts.
+ *  - Complex numbers are interleaved (re, im) pairs, FP64 unless stated.
+ *  - "host" pointers are read during the call only and copied; the caller
+ *    keeps ownership.  "device" pointers are HIP device memory owned by the
+ *    caller; the library never frees them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it; apply calls do not synchronise the host.
+ *  - A plan owns its device workspaces; they are released by the destroy call.
+ *    A plan may be used from one host thread at a time.
+ */
+#ifndef IFGF_H
+#define IFGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IFGF_OK 0
+#define IFGF_EINVAL (-1)       /* invalid argument (message says which)        */
+#define IFGF_ENOMEM (-2)       /* host or device allocation failed             */
+#define IFGF_EHIP (-3)         /* HIP runtime error (message holds its string) */
+#define IFGF_ENOTPLANNED (-4)  /* operation needs a plan that was not built    */
+#define IFGF_WNOCONV 1         /* GMRES stopped at maxit before the tolerance  */
+
+#define IFGF_FP64 0            /* cone grids, interpolation, sums in FP64      */
+#define IFGF_FP32 1            /* cone grids and interpolation in FP32         */
+
+typedef struct ifgf_plan_s* ifgf_plan_t;
+
+/* Options; ifgf_default_options() fills the paper's defaults.
+ * Ps, Pa: interpolation points per cone in the radial and in each angular
+ *   variable (Sec. III-F; Remark 2 uses 3 and 5).  0 = chosen from `tol`.
+ * ns_init, na_init: cone counts at level D+1 (Remark 2; Sec. IV uses 1, 2).
+ * refine_radial: 0 doubles only the angular cone count per level when
+ *   kappa*H_d > 1/2; 1 also doubles the radial count (literal Remark 2).
+ * leaf_wavelengths: leaf boxes satisfy H_D <= leaf_wavelengths * lambda_min
+ *   with lambda_min = 2 pi / max(k_int, k_ext) (Sec. III-G; 0.25).
+ * precision: IFGF_FP64 or IFGF_FP32.
+ * max_nrhs: largest nrhs accepted by the apply calls (sizes workspaces).
+ * host_only: 1 builds the host tables only (no device memory is touched);
+ *   such a plan serves ifgf_plan_counts/ifgf_plan_table/ifgf_stats, and the
+ *   apply calls return IFGF_ENOTPLANNED.                                    */
+typedef struct {
+  int Ps, Pa;
+  int ns_init, na_init;
+  int refine_radial;
+  double leaf_wavelengths;
+  int precision;
+  int max_nrhs;
+  int host_only;
+} ifgf_options;
+
+void ifgf_default_options(ifgf_options* opt);
+
+/* Build the IFGF plan for the discrete sums of eq. ifgf_sum_em (Sec. III-I):
+ *   out[r][q][c][l]   = sum_{m != l} w_m phi_{r,c}(x_m) G_q(x_l, x_m),        c = 0..7
+ *   out[r][q][8+c][l] = sum_{m != l} w_m phi_{r,c}(x_m) n_l . grad G_q(...), c = 0..5
+ * with G_q(x,y) = exp(i k_q |x-y|)/(4 pi |x-y|), k_0 = k_int, k_1 = k_ext.
+ *  n        number of points (>= 1)
+ *  points   host [n][3] FP64, pairwise different (Sec. III-E)
+ *  normals  host [n][3] FP64 unit normals (|n| within 1e-6 of 1)
+ *  weights  host [n] FP64 quadrature weights (> 0), e.g. Fejer w_i w_j J_p
+ *  k_int, k_ext  wavenumbers (> 0)
+ *  tol      target relative accuracy in [1e-10, 1e-1]; selects Ps, Pa when
+ *           the options leave them 0
+ *  opt      NULL = defaults
+ * Errors: IFGF_EINVAL (bad sizes, NaN/Inf, non-unit normals, weights <= 0,
+ * k <= 0, tol out of range, duplicate points), IFGF_ENOMEM, IFGF_EHIP.     */
+int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points,
+              const double* normals, const double* weights, double k_int,
+              double k_ext, double tol, const ifgf_options* opt);
+
+/* Evaluate the sums above (no singular correction).
+ *  densities device [nrhs][8][n] complex (FP64), caller point order, the
+ *            unweighted densities phi (the plan applies the weights)
+ *  out       device [nrhs][2][14][n] complex (FP64), overwritten
+ * nrhs must be in [1, max_nrhs].  Errors: IFGF_EINVAL, IFGF_EHIP.           */
+int ifgf_apply(ifgf_plan_t plan, const void* densities, int nrhs, void* out,
+               void* stream);
+
+/* Plan counts (host [ncount] int64, filled up to ncount entries):
+ *  0 n, 1 D, 2 Ps, 3 Pa, 4 near pairs, 5 leaf slots, 6 leaf (point, source)
+ *  pairs, then for d = 3..D four entries per level: relevant cones, target
+ *  pairs, propagation pairs (d >= 4, else 0), ns_d * 65536 + na_d.          */
+int ifgf_plan_counts(ifgf_plan_t plan, int64_t* counts, int ncount);
+
+/* Copy plan tables to host for inspection and tests.
+ *  which = 0: sorted-position -> input-index permutation, int64 [n]
+ *  which = 1000 + d: relevant cone keys of level d, int64 box*ncones+cone
+ *  (box = Morton-ordered index of the level's non-empty boxes)
+ *  which = 2000 + d: cone slot of every (cousin target, source box) pair of
+ *  level d, ordered by sorted target then cousin list (host_only plans)
+ *  which = 3000 + d: child cone slot of every (parent interpolation point,
+ *  child box) pair propagated into level d (host_only plans).
+ * `count` receives the number of entries; `buf` may be NULL to query it.   */
+int ifgf_plan_table(ifgf_plan_t plan, int which, int64_t* buf, int64_t cap,
+                    int64_t* count);
+
+/* JSON summary of the plan and of the last apply's per-phase times (ms).   */
+int ifgf_stats(ifgf_plan_t plan, char* json, size_t cap);
+
+void ifgf_destroy(ifgf_plan_t plan);
+
+/* Thread-local message of the last failed call ("" if none).               */
+const char* ifgf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFGF_H */

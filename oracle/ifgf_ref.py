@@ -79,12 +79,28 @@ def morton_key(k: np.ndarray) -> np.ndarray:
     return key
 
 
+# Discrete decisions (which cone holds a point) evaluate theta and phi with the
+# platform C library's acos/atan2 (Python's math module), and interpolation
+# points with its sin/cos.  Symmetric surfaces put points exactly on cone
+# boundaries (e.g. phi = 3 pi / 4 on a cube-sphere diagonal); numpy's vectorised
+# transcendental functions may round such ties differently from libm, and a
+# tie broken differently changes which interpolant serves a pair.
+_acos = np.frompyfunc(math.acos, 1, 1)
+_atan2 = np.frompyfunc(math.atan2, 2, 1)
+_sin = np.frompyfunc(math.sin, 1, 1)
+_cos = np.frompyfunc(math.cos, 1, 1)
+
+
+def _f64(a):
+    return np.asarray(a, dtype=object).astype(np.float64)
+
+
 def spherical(dx, dy, dz):
-    """r, cos(theta) source of theta = arccos(dz/r), phi in [0, 2 pi)."""
+    """r, theta = arccos(dz/r) and phi = atan2(dy, dx) mapped to [0, 2 pi)."""
     r = np.sqrt(dx * dx + dy * dy + dz * dz)
     ct = np.clip(dz / r, -1.0, 1.0)
-    th = np.arccos(ct)
-    ph = np.arctan2(dy, dx)
+    th = _f64(_acos(ct))
+    ph = _f64(_atan2(dy, dx))
     ph = np.where(ph < 0.0, ph + TWO_PI, ph)
     return r, th, ph
 
@@ -228,8 +244,8 @@ class Tree:
         S, Th, Ph = self.cone_nodes(d, cone_ids)
         n = cone_ids.size
         rr = (L.h / S).reshape(n, -1)
-        st, ct = np.sin(Th).reshape(n, -1), np.cos(Th).reshape(n, -1)
-        sp, cp = np.sin(Ph).reshape(n, -1), np.cos(Ph).reshape(n, -1)
+        st, ct = _f64(_sin(Th)).reshape(n, -1), _f64(_cos(Th)).reshape(n, -1)
+        sp, cp = _f64(_sin(Ph)).reshape(n, -1), _f64(_cos(Ph)).reshape(n, -1)
         c = L.centers[boxes]
         X = np.empty((n, rr.shape[1], 3))
         X[..., 0] = c[:, None, 0] + rr * (st * cp)

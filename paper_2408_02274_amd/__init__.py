@@ -1,0 +1,10 @@
+"""MI355X-native IFGF-accelerated N-Mueller boundary-integral operator.
+
+The compute lives in the HIP/C++ library libifgf.so (C-ABI in include/ifgf.h);
+`binding` marshals torch/numpy arguments to it.
+"""
+from .binding import (IFGFError, IFGFPlan, ifgf_apply, ifgf_destroy, ifgf_plan,
+                      ifgf_plan_counts, ifgf_plan_table, ifgf_stats, lib)
+
+__all__ = ["IFGFError", "IFGFPlan", "ifgf_apply", "ifgf_destroy", "ifgf_plan",
+           "ifgf_plan_counts", "ifgf_plan_table", "ifgf_stats", "lib"]

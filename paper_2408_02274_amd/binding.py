@@ -1,0 +1,189 @@
+"""ctypes binding of libifgf (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts torch
+tensors and numpy arrays into the pointers and sizes of the C-ABI declared in
+include/ifgf.h and raises on any non-zero status.  If the shared library is
+missing the import fails loudly: there is no Python fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libifgf.so")
+
+IFGF_FP64 = 0
+IFGF_FP32 = 1
+IFGF_WNOCONV = 1
+
+
+class IFGFError(RuntimeError):
+    pass
+
+
+class Options(C.Structure):
+    _fields_ = [("Ps", C.c_int), ("Pa", C.c_int), ("ns_init", C.c_int), ("na_init", C.c_int),
+                ("refine_radial", C.c_int), ("leaf_wavelengths", C.c_double),
+                ("precision", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libifgf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # torch ships its own libamdhip64.so.7; libifgf.so needs the same soname.
+        # Loading torch first makes the process use one HIP runtime: the one
+        # that owns the device memory and streams handed to the library.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libifgf.so not found at {LIB_PATH}: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, dbl, ci = C.c_void_p, C.c_int64, C.c_double, C.c_int
+        L.ifgf_default_options.argtypes = [C.POINTER(Options)]
+        L.ifgf_default_options.restype = None
+        L.ifgf_plan.argtypes = [C.POINTER(vp), i64, vp, vp, vp, dbl, dbl, dbl, C.POINTER(Options)]
+        L.ifgf_apply.argtypes = [vp, vp, ci, vp, vp]
+        L.ifgf_plan_counts.argtypes = [vp, C.POINTER(i64), ci]
+        L.ifgf_plan_table.argtypes = [vp, ci, C.POINTER(i64), i64, C.POINTER(i64)]
+        L.ifgf_stats.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.ifgf_destroy.argtypes = [vp]
+        L.ifgf_destroy.restype = None
+        L.ifgf_last_error.restype = C.c_char_p
+        for name in ("ifgf_plan", "ifgf_apply", "ifgf_plan_counts", "ifgf_plan_table", "ifgf_stats"):
+            getattr(L, name).restype = ci
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names of the C-ABI entry points declared in include/ifgf.h."""
+    hdr = os.path.join(os.path.dirname(_HERE), "include")
+    names = []
+    import re
+    for f in sorted(os.listdir(hdr)):
+        if f.endswith(".h"):
+            txt = open(os.path.join(hdr, f)).read()
+            names += re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    return names
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise IFGFError(f"{what} failed ({rc}): {lib().ifgf_last_error().decode()}")
+    return rc
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+def _host_f64(a, shape):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def default_options():
+    o = Options()
+    lib().ifgf_default_options(C.byref(o))
+    return o
+
+
+def ifgf_plan(points, normals, weights, k_int, k_ext, tol=1e-4, **opts):
+    """Build an IFGF plan; returns an opaque handle (int)."""
+    x = np.asarray(points)
+    n = x.shape[0]
+    x = _host_f64(points, (n, 3))
+    nr = _host_f64(normals, (n, 3))
+    w = _host_f64(weights, (n,))
+    o = default_options()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    h = C.c_void_p()
+    _check(lib().ifgf_plan(C.byref(h), n, x.ctypes.data, nr.ctypes.data, w.ctypes.data,
+                           float(k_int), float(k_ext), float(tol), C.byref(o)), "ifgf_plan")
+    return h.value
+
+
+def ifgf_apply(plan, densities, nrhs, out, stream=None):
+    """densities: device [nrhs][8][n] complex128; out: device [nrhs][2][14][n] complex128."""
+    _check(lib().ifgf_apply(plan, densities.data_ptr(), int(nrhs), out.data_ptr(),
+                            _stream_ptr(stream)), "ifgf_apply")
+
+
+def ifgf_plan_counts(plan, ncount=64):
+    buf = (C.c_int64 * ncount)()
+    _check(lib().ifgf_plan_counts(plan, buf, ncount), "ifgf_plan_counts")
+    return list(buf)
+
+
+def ifgf_plan_table(plan, which):
+    cnt = C.c_int64()
+    _check(lib().ifgf_plan_table(plan, int(which), None, 0, C.byref(cnt)), "ifgf_plan_table")
+    arr = np.zeros(cnt.value, dtype=np.int64)
+    _check(lib().ifgf_plan_table(plan, int(which), arr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 cnt.value, C.byref(cnt)), "ifgf_plan_table")
+    return arr
+
+
+def ifgf_stats(plan):
+    import json
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().ifgf_stats(plan, buf, len(buf)), "ifgf_stats")
+    return json.loads(buf.value.decode())
+
+
+def ifgf_destroy(plan):
+    if plan:
+        lib().ifgf_destroy(plan)
+
+
+class IFGFPlan:
+    """Owning wrapper around an ifgf plan handle."""
+
+    def __init__(self, points, normals, weights, k_int, k_ext, tol=1e-4, **opts):
+        self.n = int(np.asarray(points).shape[0])
+        self.max_nrhs = int(opts.get("max_nrhs", 1))
+        self.handle = ifgf_plan(points, normals, weights, k_int, k_ext, tol, **opts)
+
+    def apply(self, densities, out=None, stream=None):
+        import torch
+        nrhs = densities.shape[0]
+        if densities.dtype != torch.complex128 or not densities.is_contiguous():
+            raise ValueError("densities must be a contiguous complex128 device tensor")
+        if tuple(densities.shape[1:]) != (8, self.n):
+            raise ValueError(f"densities must have shape [nrhs, 8, {self.n}]")
+        if out is None:
+            out = torch.empty((nrhs, 2, 14, self.n), dtype=torch.complex128, device=densities.device)
+        ifgf_apply(self.handle, densities, nrhs, out, stream)
+        return out
+
+    def counts(self):
+        return ifgf_plan_counts(self.handle)
+
+    def table(self, which):
+        return ifgf_plan_table(self.handle, which)
+
+    def stats(self):
+        return ifgf_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            ifgf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,357 @@
+// C-ABI of libifgf: plan construction, upload and the IFGF apply driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ifgf.h"
+#include "device.hpp"
+#include "plan.hpp"
+#include "util.hpp"
+
+using namespace ifgf;
+
+struct ifgf_plan_s {
+  HostPlan host;
+  ifgf_options opt;
+  InterpC ic;
+  int device = 0;
+  // device copies
+  DeviceArena arena;
+  int64_t* d_perm = nullptr;
+  double* d_xs = nullptr;
+  double* d_nrm = nullptr;
+  double* d_w = nullptr;
+  int32_t* d_leaf_of_point = nullptr;
+  std::vector<DevLevel> lev;   // lev[d]
+  // workspaces
+  double2* d_a = nullptr;      // [n][8]
+  double2* d_out_s = nullptr;  // [n][28]
+  double2* d_vals[2] = {nullptr, nullptr};
+  int64_t max_slots = 0;
+};
+
+namespace {
+
+int tol_to_orders(double tol, int* Ps, int* Pa) {
+  // Paper setting (Remark 2): Ps = 3, Pa = 5.  Tighter tolerances raise the
+  // radial order first, which dominates the interpolation error.
+  if (tol >= 1e-3) { *Ps = 3; *Pa = 5; }
+  else if (tol >= 1e-4) { *Ps = 5; *Pa = 5; }
+  else if (tol >= 1e-5) { *Ps = 5; *Pa = 7; }
+  else { *Ps = 7; *Pa = 8; }
+  return 0;
+}
+
+void make_interp(InterpC& ic, int Ps, int Pa) {
+  ic.Ps = Ps;
+  ic.Pa = Pa;
+  ic.npts = Ps * Pa * Pa;
+  auto fill = [](int P, double* x, double* w) {
+    for (int k = 0; k < P; ++k) x[k] = std::cos((k + 0.5) * 3.141592653589793 / P);
+    for (int j = 0; j < P; ++j) {
+      double p = 1.0;
+      for (int m = 0; m < P; ++m)
+        if (m != j) p *= (x[j] - x[m]);
+      w[j] = 1.0 / p;
+    }
+  };
+  std::memset(ic.xs, 0, sizeof(ic.xs));
+  std::memset(ic.xa, 0, sizeof(ic.xa));
+  std::memset(ic.ws, 0, sizeof(ic.ws));
+  std::memset(ic.wa, 0, sizeof(ic.wa));
+  fill(Ps, ic.xs, ic.ws);
+  fill(Pa, ic.xa, ic.wa);
+}
+
+template <class T>
+int upload(DeviceArena& ar, const std::vector<T>& v, T** dst) {
+  *dst = nullptr;
+  if (v.empty()) return 0;
+  *dst = static_cast<T*>(ar.alloc(v.size() * sizeof(T)));
+  if (!*dst) return IFGF_ENOMEM;
+  hipError_t e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return set_hip_error(e, "hipMemcpy");
+  return 0;
+}
+
+int validate(int64_t n, const double* x, const double* nrm, const double* w, double k0, double k1,
+             double tol) {
+  if (n < 1) return set_error(IFGF_EINVAL, "n must be >= 1");
+  if (!x || !nrm || !w) return set_error(IFGF_EINVAL, "points, normals and weights are required");
+  if (!(k0 > 0.0) || !(k1 > 0.0) || !std::isfinite(k0) || !std::isfinite(k1))
+    return set_error(IFGF_EINVAL, "wavenumbers must be finite and > 0");
+  if (!(tol >= 1e-10 && tol <= 1e-1)) return set_error(IFGF_EINVAL, "tol must lie in [1e-10, 1e-1]");
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(x[3 * i + c]) || !std::isfinite(nrm[3 * i + c]))
+        return set_error(IFGF_EINVAL, "non-finite point or normal at index " + std::to_string(i));
+    double nn = std::sqrt(nrm[3 * i] * nrm[3 * i] + nrm[3 * i + 1] * nrm[3 * i + 1] +
+                          nrm[3 * i + 2] * nrm[3 * i + 2]);
+    if (std::fabs(nn - 1.0) > 1e-6)
+      return set_error(IFGF_EINVAL, "normal is not unit length at index " + std::to_string(i));
+    if (!(w[i] > 0.0) || !std::isfinite(w[i]))
+      return set_error(IFGF_EINVAL, "weight must be finite and > 0 at index " + std::to_string(i));
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ifgf_default_options(ifgf_options* opt) {
+  if (!opt) return;
+  opt->Ps = 0;
+  opt->Pa = 0;
+  opt->ns_init = 1;
+  opt->na_init = 2;
+  opt->refine_radial = 0;
+  opt->leaf_wavelengths = 0.25;
+  opt->precision = IFGF_FP64;
+  opt->max_nrhs = 1;
+  opt->host_only = 0;
+}
+
+int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* normals,
+              const double* weights, double k_int, double k_ext, double tol,
+              const ifgf_options* optin) {
+  clear_error();
+  if (!out) return set_error(IFGF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(n, points, normals, weights, k_int, k_ext, tol);
+  if (rc) return rc;
+  ifgf_options opt;
+  ifgf_default_options(&opt);
+  if (optin) opt = *optin;
+  if (opt.ns_init <= 0) opt.ns_init = 1;
+  if (opt.na_init <= 0) opt.na_init = 2;
+  if (opt.leaf_wavelengths <= 0.0) opt.leaf_wavelengths = 0.25;
+  if (opt.max_nrhs <= 0) opt.max_nrhs = 1;
+  if (opt.Ps <= 0 || opt.Pa <= 0) tol_to_orders(tol, &opt.Ps, &opt.Pa);
+  if (opt.Ps > kMaxP || opt.Pa > kMaxP || opt.Ps < 1 || opt.Pa < 1)
+    return set_error(IFGF_EINVAL, "Ps and Pa must lie in [1, 8]");
+  if (opt.precision != IFGF_FP64 && opt.precision != IFGF_FP32)
+    return set_error(IFGF_EINVAL, "precision must be IFGF_FP64 or IFGF_FP32");
+
+  ifgf_plan_s* p = new (std::nothrow) ifgf_plan_s();
+  if (!p) return set_error(IFGF_ENOMEM, "host allocation failed");
+  p->opt = opt;
+  PlanParams pp;
+  pp.Ps = opt.Ps;
+  pp.Pa = opt.Pa;
+  pp.ns_init = opt.ns_init;
+  pp.na_init = opt.na_init;
+  pp.refine_radial = opt.refine_radial;
+  pp.leaf_wavelengths = opt.leaf_wavelengths;
+  std::string err;
+  try {
+    if (build_host_plan(p->host, n, points, normals, weights, k_int, k_ext, pp, err)) {
+      delete p;
+      return set_error(IFGF_EINVAL, err);
+    }
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return set_error(IFGF_ENOMEM, "host allocation failed while planning");
+  }
+  HostPlan& H = p->host;
+  // duplicate points (excluded by the method: Sec. III-E) share a leaf
+  {
+    HostLevel& L = H.lev[H.D];
+    for (int64_t b = 0; b < L.nb; ++b)
+      for (int32_t i = L.start[b]; i < L.end[b]; ++i)
+        for (int32_t j = i + 1; j < L.end[b]; ++j)
+          if (H.xs[3 * i] == H.xs[3 * j] && H.xs[3 * i + 1] == H.xs[3 * j + 1] &&
+              H.xs[3 * i + 2] == H.xs[3 * j + 2]) {
+            delete p;
+            return set_error(IFGF_EINVAL, "duplicate points (input indices " +
+                                              std::to_string(H.perm[i]) + ", " +
+                                              std::to_string(H.perm[j]) + ")");
+          }
+  }
+  make_interp(p->ic, opt.Ps, opt.Pa);
+  if (opt.host_only) {
+    *out = p;
+    return IFGF_OK;
+  }
+  (void)hipGetDevice(&p->device);
+
+  DeviceArena& ar = p->arena;
+  if ((rc = upload(ar, H.perm, &p->d_perm)) || (rc = upload(ar, H.xs, &p->d_xs)) ||
+      (rc = upload(ar, H.nrm, &p->d_nrm)) || (rc = upload(ar, H.w, &p->d_w)) ||
+      (rc = upload(ar, H.leaf_of_point, &p->d_leaf_of_point))) {
+    delete p;
+    return rc;
+  }
+  p->lev.assign(H.D + 1, DevLevel());
+  for (int d = 1; d <= H.D; ++d) {
+    HostLevel& L = H.lev[d];
+    DevLevel& G = p->lev[d];
+    G.d = d;
+    G.h = L.h;
+    G.ns = L.ns;
+    G.na = L.na;
+    G.nb = L.nb;
+    G.nslots = L.nslots;
+    if ((rc = upload(ar, L.centers, &G.centers)) || (rc = upload(ar, L.start, &G.start)) ||
+        (rc = upload(ar, L.end, &G.end)) || (rc = upload(ar, L.child_start, &G.child_start)) ||
+        (rc = upload(ar, L.child_end, &G.child_end)) || (rc = upload(ar, L.slot_box, &G.slot_box)) ||
+        (rc = upload(ar, L.slot_cone, &G.slot_cone)) || (rc = upload(ar, L.tp_off, &G.tp_off)) ||
+        (rc = upload(ar, L.tp_slot, &G.tp_slot)) || (rc = upload(ar, L.pp_off, &G.pp_off)) ||
+        (rc = upload(ar, L.pp_slot, &G.pp_slot))) {
+      delete p;
+      return rc;
+    }
+    if (d == H.D) {
+      if ((rc = upload(ar, L.nbr_off, &G.nbr_off)) || (rc = upload(ar, L.nbr, &G.nbr))) {
+        delete p;
+        return rc;
+      }
+    }
+    if (d >= 3) p->max_slots = std::max(p->max_slots, L.nslots);
+    // the host copies of the large pair tables are no longer needed
+    std::vector<int32_t>().swap(L.tp_slot);
+    std::vector<int32_t>().swap(L.pp_slot);
+  }
+  p->d_a = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kNS));
+  p->d_out_s = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kOut));
+  if (!p->d_a || !p->d_out_s) {
+    delete p;
+    return set_error(IFGF_ENOMEM, "device workspace allocation failed");
+  }
+  if (p->max_slots > 0) {
+    size_t vb = sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
+    p->d_vals[0] = static_cast<double2*>(ar.alloc(vb));
+    p->d_vals[1] = static_cast<double2*>(ar.alloc(vb));
+    if (!p->d_vals[0] || !p->d_vals[1]) {
+      delete p;
+      return set_error(IFGF_ENOMEM, "device cone-grid allocation failed");
+    }
+  }
+  *out = p;
+  return IFGF_OK;
+}
+
+int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* stream) {
+  clear_error();
+  if (!p) return set_error(IFGF_EINVAL, "plan is NULL");
+  if (!densities || !out) return set_error(IFGF_EINVAL, "densities and out are required");
+  if (nrhs < 1 || nrhs > p->opt.max_nrhs)
+    return set_error(IFGF_EINVAL, "nrhs must lie in [1, max_nrhs]");
+  if (p->opt.host_only) return set_error(IFGF_ENOTPLANNED, "plan was built with host_only");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const HostPlan& H = p->host;
+  const int64_t n = H.n;
+  const double k0 = H.k[0], k1 = H.k[1];
+  for (int r = 0; r < nrhs; ++r) {
+    const double2* dens = static_cast<const double2*>(densities) + (int64_t)r * kNS * n;
+    double2* o = static_cast<double2*>(out) + (int64_t)r * kOut * n;
+    hipError_t e;
+    if ((e = launch_gather_weighted(dens, p->d_perm, p->d_w, n, p->d_a, st)) != hipSuccess)
+      return set_hip_error(e, "gather");
+    if ((e = launch_near(p->lev[H.D], p->d_leaf_of_point, p->d_xs, p->d_nrm, p->d_a, n, k0, k1,
+                         p->d_out_s, st)) != hipSuccess)
+      return set_hip_error(e, "near");
+    if (H.D >= 3) {
+      int cur = 0;
+      if ((e = launch_leaf(p->lev[H.D], p->ic, p->d_xs, p->d_a, k0, k1, p->d_vals[cur], st)) !=
+          hipSuccess)
+        return set_hip_error(e, "leaf");
+      for (int d = H.D; d >= 3; --d) {
+        if ((e = launch_targets(p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1, p->d_vals[cur],
+                                p->d_out_s, st)) != hipSuccess)
+          return set_hip_error(e, "targets");
+        if (d > 3) {
+          if ((e = launch_propagate(p->lev[d], p->lev[d - 1], p->ic, k0, k1, p->d_vals[cur],
+                                    p->d_vals[cur ^ 1], st)) != hipSuccess)
+            return set_hip_error(e, "propagate");
+          cur ^= 1;
+        }
+      }
+    }
+    if ((e = launch_scatter_out(p->d_out_s, p->d_perm, n, o, st)) != hipSuccess)
+      return set_hip_error(e, "scatter");
+  }
+  return IFGF_OK;
+}
+
+int ifgf_plan_counts(ifgf_plan_t p, int64_t* counts, int ncount) {
+  clear_error();
+  if (!p || !counts) return set_error(IFGF_EINVAL, "plan and counts are required");
+  const HostPlan& H = p->host;
+  std::vector<int64_t> v = {H.n, H.D, H.Ps, H.Pa, H.near_pairs,
+                            H.D >= 3 ? H.lev[H.D].nslots : 0, H.leaf_pairs};
+  for (int d = 3; d <= H.D; ++d) {
+    const HostLevel& L = H.lev[d];
+    int64_t tp = L.tp_off.empty() ? 0 : L.tp_off.back();
+    int64_t pp = (d >= 4 && !H.lev[d - 1].pp_off.empty()) ? H.lev[d - 1].pp_off.back() : 0;
+    v.push_back(L.nslots);
+    v.push_back(tp);
+    v.push_back(pp);
+    v.push_back((int64_t)L.ns * 65536 + L.na);
+  }
+  for (int i = 0; i < ncount; ++i) counts[i] = i < (int)v.size() ? v[i] : 0;
+  return IFGF_OK;
+}
+
+int ifgf_plan_table(ifgf_plan_t p, int which, int64_t* buf, int64_t cap, int64_t* count) {
+  clear_error();
+  if (!p || !count) return set_error(IFGF_EINVAL, "plan and count are required");
+  const HostPlan& H = p->host;
+  std::vector<int64_t> v;
+  if (which == 0) {
+    v = H.perm;
+  } else if (which > 1000 && which - 1000 <= H.D && which - 1000 >= 3) {
+    const HostLevel& L = H.lev[which - 1000];
+    v.resize(L.nslots);
+    for (int64_t s = 0; s < L.nslots; ++s) v[s] = (int64_t)L.slot_box[s] * L.ncones + L.slot_cone[s];
+  } else if (which > 2000 && which - 2000 <= H.D && which - 2000 >= 3) {
+    const HostLevel& L = H.lev[which - 2000];
+    if (L.tp_slot.size() != (size_t)(L.tp_off.empty() ? 0 : L.tp_off.back()))
+      return set_error(IFGF_ENOTPLANNED, "pair tables are kept only by host_only plans");
+    v.assign(L.tp_slot.begin(), L.tp_slot.end());
+  } else if (which > 3000 && which - 3000 < H.D && which - 3000 >= 3) {
+    const HostLevel& L = H.lev[which - 3000];
+    if (L.pp_slot.size() != (size_t)(L.pp_off.empty() ? 0 : L.pp_off.back()))
+      return set_error(IFGF_ENOTPLANNED, "pair tables are kept only by host_only plans");
+    v.assign(L.pp_slot.begin(), L.pp_slot.end());
+  } else {
+    return set_error(IFGF_EINVAL, "unknown table id");
+  }
+  *count = (int64_t)v.size();
+  if (buf) {
+    if (cap < (int64_t)v.size()) return set_error(IFGF_EINVAL, "buffer too small");
+    std::memcpy(buf, v.data(), v.size() * sizeof(int64_t));
+  }
+  return IFGF_OK;
+}
+
+int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
+  clear_error();
+  if (!p || !json) return set_error(IFGF_EINVAL, "plan and json are required");
+  const HostPlan& H = p->host;
+  std::string s = "{\"n\":" + std::to_string(H.n) + ",\"D\":" + std::to_string(H.D) +
+                  ",\"Ps\":" + std::to_string(H.Ps) + ",\"Pa\":" + std::to_string(H.Pa) +
+                  ",\"near_pairs\":" + std::to_string(H.near_pairs) +
+                  ",\"leaf_pairs\":" + std::to_string(H.leaf_pairs) +
+                  ",\"device_bytes\":" + std::to_string(p->arena.bytes()) + ",\"levels\":[";
+  for (int d = 3; d <= H.D; ++d) {
+    const HostLevel& L = H.lev[d];
+    s += std::string(d > 3 ? "," : "") + "{\"d\":" + std::to_string(d) + ",\"boxes\":" +
+         std::to_string(L.nb) + ",\"ns\":" + std::to_string(L.ns) + ",\"na\":" +
+         std::to_string(L.na) + ",\"slots\":" + std::to_string(L.nslots) + "}";
+  }
+  s += "]}";
+  if (s.size() + 1 > cap) return set_error(IFGF_EINVAL, "json buffer too small");
+  std::memcpy(json, s.c_str(), s.size() + 1);
+  return IFGF_OK;
+}
+
+void ifgf_destroy(ifgf_plan_t p) { delete p; }
+
+const char* ifgf_last_error(void) { return last_error_cstr(); }
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Host-side IFGF plan: box octree, cone structure and relevant-cone tables.
+//
+// Paper: Sec. III-F (cone segments), Sec. III-G (octree, neighbours, cousins,
+// relevant cones eq. rele_cone, Remark 2 cone counts, algorithm step 1).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ifgf {
+
+constexpr int kMaxP = 8;      // largest Ps / Pa supported by the kernels
+
+struct HostLevel {
+  int d = 0;
+  double H = 0.0, h = 0.0;     // box side and radius h = sqrt(3) H / 2
+  int ns = 0, na = 0;          // cone counts (levels >= 3)
+  int64_t ncones = 0;          // ns * na * 2 na
+  int64_t nb = 0;              // non-empty ("relevant") boxes, Morton order
+  std::vector<int64_t> key;
+  std::vector<int32_t> coords;             // [nb][3] integer box coordinates
+  std::vector<double> centers;             // [nb][3]
+  std::vector<int32_t> start, end;         // point range in sorted order
+  std::vector<int32_t> parent;             // box index at level d-1
+  std::vector<int32_t> child_start, child_end;  // box range at level d+1
+  std::vector<int32_t> nbr_off, nbr;       // neighbours (CSR, self included)
+  std::vector<int32_t> cous_off, cous;     // cousins (CSR), levels >= 3
+  // relevant cones, slots ordered by (box, cone)
+  std::vector<int64_t> slot_off;           // [nb+1]
+  std::vector<int32_t> slot_cone, slot_box;
+  int64_t nslots = 0;
+  // interpolation onto cousin points: for sorted target i, the relevant cone
+  // slot of each cousin box of box(i), in cousin-list order
+  std::vector<int64_t> tp_off;             // [n+1]
+  std::vector<int32_t> tp_slot;
+  // propagation (levels >= 4): for parent slot q at level d-1, child j of its
+  // box and interpolation point k, the child's cone slot at level d
+  std::vector<int64_t> pp_off;             // [nslots(d-1)+1], stride nchild*npts
+  std::vector<int32_t> pp_slot;
+};
+
+struct HostPlan {
+  int64_t n = 0;
+  double k[2] = {0.0, 0.0};
+  double kmax = 0.0;
+  int Ps = 3, Pa = 5, npts = 75;
+  int D = 1;
+  double H1 = 1.0;
+  double center[3] = {0, 0, 0}, origin[3] = {0, 0, 0};
+  std::vector<int64_t> perm;               // sorted position -> input index
+  std::vector<double> xs, nrm, w;          // sorted points, normals, weights
+  std::vector<HostLevel> lev;              // lev[d], d = 1..D
+  std::vector<int32_t> leaf_of_point;      // sorted point -> leaf box
+  int64_t near_pairs = 0, leaf_pairs = 0;
+};
+
+struct PlanParams {
+  int Ps = 3, Pa = 5, ns_init = 1, na_init = 2, refine_radial = 0;
+  double leaf_wavelengths = 0.25;
+};
+
+// Returns 0 on success, else fills err.
+int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
+                    const double* w, double k0, double k1, const PlanParams& pp,
+                    std::string& err);
+
+// Cone index of the offset (dx,dy,dz) from a box centre (box radius h) with
+// ns x na x 2na cones; also returns s, theta, phi.
+int cone_index(double dx, double dy, double dz, double h, int ns, int na,
+               double* s, double* th, double* ph);
+
+}  // namespace ifgf

@@ -1,0 +1,95 @@
+"""GPU parity of ifgf_apply (FP64) against the oracle.
+
+Bar: the FP64 GPU IFGF equals the reference IFGF (O2) to 1e-10 relative L2
+(same algorithm, rounding order only), and stays within the IFGF error of
+the direct O(N^2) sum (O1).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, ifgf_ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _gpu_apply(x, n, w, ks, phi, **opt):
+    from paper_2408_02274_amd import IFGFPlan
+    nrhs = phi.shape[0]
+    plan = IFGFPlan(x, n, w, ks[0], ks[1], opt.pop("tol", 1e-3), max_nrhs=nrhs, **opt)
+    d = torch.from_numpy(np.ascontiguousarray(phi)).to("cuda")
+    out = plan.apply(d)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    plan.close()
+    return res
+
+
+CASES = {
+    "sphere864": lambda: (synth.cube_sphere(2, 6, 1.0), (1.5 * math.pi, 1.0 * math.pi)),
+    "sphere_c1": lambda: (synth.cube_sphere(2, 8, 1.0), (3 * math.pi, 2 * math.pi)),
+    "ellipsoid": lambda: (synth.ellipsoid(1.2, 0.7, 0.9, 2, 6), (3.0 * math.pi, 2.0 * math.pi)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("order", [(3, 5), (5, 5)])
+def test_fp64_matches_reference_ifgf(case, order):
+    s, ks = CASES[case]()
+    rng = np.random.default_rng(21)
+    w = rng.uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 22)
+    Ps, Pa = order
+    _say(f"[gpu] ifgf fp64 {case} n={s.n} Ps={Ps} Pa={Pa}")
+    g = _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa)[0]
+    o2 = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params(Ps=Ps, Pa=Pa)).apply(phi[0])
+    for q in range(2):
+        assert _rel(g[q, :8], o2[q, :8]) < 1e-10
+        assert _rel(g[q, 8:], o2[q, 8:]) < 1e-10
+    o1 = direct.regular_sums(s.x, s.normal, w, phi[0], ks)
+    bound = (3e-3, 1e-2) if order == (3, 5) else (2e-4, 2e-3)
+    for q in range(2):
+        assert _rel(g[q, :8], o1[q, :8]) < bound[0]
+        assert _rel(g[q, 8:], o1[q, 8:]) < bound[1]
+
+
+def test_fp64_counting_free_cloud_and_nrhs():
+    # volumetric cloud: many cousins per box; three right-hand sides in one call
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, (1200, 3))
+    nrm = rng.standard_normal((1200, 3))
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    w = rng.uniform(0.2, 1.0, 1200)
+    ks = (6.0, 4.0)
+    phi = synth.complex_normal((3, 8, 1200), 32)
+    _say("[gpu] ifgf fp64 cloud n=1200 nrhs=3")
+    g = _gpu_apply(x, nrm, w, ks, phi, Ps=3, Pa=5)
+    ref = ifgf_ref.ReferenceIFGF(x, nrm, w, ks, ifgf_ref.Params(Ps=3, Pa=5))
+    for r in range(3):
+        o2 = ref.apply(phi[r])
+        assert _rel(g[r], o2) < 1e-10
+
+
+@pytest.mark.parametrize("npts", [1, 2, 7, 40])
+def test_fp64_tiny_inputs_are_exact_direct_sums(npts):
+    # tiny inputs have D <= 2 (everything near): the output is the direct sum
+    rng = np.random.default_rng(npts)
+    x = rng.uniform(-0.05, 0.05, (npts, 3))
+    nrm = np.tile([0.0, 0.0, 1.0], (npts, 1))
+    w = np.ones(npts)
+    phi = synth.complex_normal((1, 8, npts), 41)
+    _say(f"[gpu] ifgf fp64 tiny n={npts}")
+    g = _gpu_apply(x, nrm, w, (3.0, 2.0), phi)[0]
+    o1 = direct.regular_sums(x, nrm, w, phi[0], (3.0, 2.0))
+    assert np.allclose(g, o1, rtol=1e-12, atol=1e-14)
