@@ -112,13 +112,83 @@ int ifgf_plan_counts(ifgf_plan_t plan, int64_t* counts, int ncount);
 int ifgf_plan_table(ifgf_plan_t plan, int which, int64_t* buf, int64_t cap,
                     int64_t* count);
 
-/* JSON summary of the plan and of the last apply's per-phase times (ms).   */
+/* JSON summary of the plan; with timing on, also per-kernel launch counts,
+ * summed durations (ms, from HIP events on the apply stream) and summed work
+ * units (pairs or points) since timing was switched on.  Reading the timing
+ * synchronises on the recorded events.                                     */
 int ifgf_stats(ifgf_plan_t plan, char* json, size_t cap);
+
+/* Switch per-kernel timing on (1) or off (0); either resets the totals.    */
+int ifgf_set_timing(ifgf_plan_t plan, int on);
 
 void ifgf_destroy(ifgf_plan_t plan);
 
 /* Thread-local message of the last failed call ("" if none).               */
 const char* ifgf_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * N-Mueller operator (Sec. II eq. n_muller, k_delta, r_delta, t_delta) on a
+ * patch surface discretised by open Chebyshev grids (Sec. III-A).
+ * Point order l = j + Nc*i + p*Nc^2 with x_l = eta_p(u_i, v_j),
+ * u_k = cos((k + 1/2) pi / Nc) (eq. cheby_nodes, mesh_pts_l).
+ * Unknowns y[r][4][n] = (m.t1, m.t2, j.t1, j.t2) with t1 = d_u eta/|d_u eta|,
+ * t2 = n x t1, n = d_u eta x d_v eta / |.| (outward when the caller orients
+ * the patches so).  Wavenumbers k_s = omega sqrt(eps_s mu_s).
+ * ------------------------------------------------------------------------- */
+typedef struct nmuller_s* nmuller_t;
+
+/* P, Nc: patches and nodes per direction (2 <= Nc <= 16), n = P Nc^2.
+ * eps_e, eps_i, mu_e, mu_i: exterior/interior permittivity and permeability.
+ * omega: angular frequency (lengths in vacuum wavelengths give 2 pi).
+ * delta_factor: singular set S_l = {p : dist(x_l, Gamma_p) <= delta_p} with
+ *   delta_p = delta_factor x diagonal of the patch's node bounding box
+ *   (Sec. III-B eq. patch_sing; 0 -> 1.0).
+ * nbeta: Fejer points per direction of the singular rule (eq. int_moments_cov;
+ *   0 -> 6 Nc).  d_cov: parameter d of the sigmoidal map (eq. mk_cov_1; 4).  */
+typedef struct {
+  int P, Nc;
+  double eps_e, eps_i, mu_e, mu_i;
+  double omega;
+  double delta_factor;
+  int nbeta;
+  int d_cov;
+} nmuller_params;
+
+void nmuller_default_params(nmuller_params* p);
+
+/* Build the operator: surface quantities (normals, Jacobians, Fejer weights
+ * w_i w_j J), the IFGF plan of the regular sums at (k_int, k_ext) and the
+ * near-field corrections (Sec. III-D singular moments minus the regular Fejer
+ * weights, Sec. III-H), the latter kept in FP64.
+ *  points, du, dv  host [n][3] FP64: nodes and d eta/du, d eta/dv there
+ *  tol, opt        as for ifgf_plan (opt->host_only builds host tables only)
+ * Errors: IFGF_EINVAL, IFGF_ENOMEM, IFGF_EHIP.                               */
+int nmuller_plan(nmuller_t* out, const nmuller_params* prm, const double* points,
+                 const double* du, const double* dv, double tol, const ifgf_options* opt);
+
+/* Ay = A y for y device [nrhs][4][n] complex FP64; Ay device, same shape.   */
+int nmuller_apply(nmuller_t nm, const void* y, int nrhs, void* Ay, void* stream);
+
+/* Right-hand side of eq. n_muller: b = omega^-1 (n x E, n x H) projected on
+ * (t1, t2).  E, H device [nrhs][n][3] complex FP64 (incident fields at the
+ * nodes); b device [nrhs][4][n].                                           */
+int nmuller_rhs(nmuller_t nm, const void* E, const void* H, int nrhs, void* b, void* stream);
+
+/* Host copies of surface quantities: which = 0 normals [n][3], 1 weights [n],
+ * 2 t1 [n][3], 3 t2 [n][3], 4 Jacobians [n].                                */
+int nmuller_geometry(nmuller_t nm, int which, double* buf, int64_t cap);
+
+/* Near-field corrections: npairs receives the number of (target, patch)
+ * pairs; row_off [n+1], pair_patch [npairs] and vals [npairs][4][Nc^2][2]
+ * (kernel order S k_int, S k_ext, D k_int, D k_ext; FP64 re/im) are filled
+ * when non-NULL.  vals are available from host_only plans only.             */
+int nmuller_corrections(nmuller_t nm, int64_t* npairs, int64_t* row_off,
+                        int32_t* pair_patch, double* vals);
+
+/* The IFGF plan used by the operator (owned by nm).                         */
+ifgf_plan_t nmuller_ifgf(nmuller_t nm);
+
+void nmuller_destroy(nmuller_t nm);
 
 #ifdef __cplusplus
 }

@@ -30,6 +30,12 @@ class Options(C.Structure):
                 ("precision", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int)]
 
 
+class NMullerParams(C.Structure):
+    _fields_ = [("P", C.c_int), ("Nc", C.c_int), ("eps_e", C.c_double), ("eps_i", C.c_double),
+                ("mu_e", C.c_double), ("mu_i", C.c_double), ("omega", C.c_double),
+                ("delta_factor", C.c_double), ("nbeta", C.c_int), ("d_cov", C.c_int)]
+
+
 _lib = None
 
 
@@ -52,10 +58,26 @@ def lib():
         L.ifgf_plan_counts.argtypes = [vp, C.POINTER(i64), ci]
         L.ifgf_plan_table.argtypes = [vp, ci, C.POINTER(i64), i64, C.POINTER(i64)]
         L.ifgf_stats.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.ifgf_set_timing.argtypes = [vp, ci]
+        L.ifgf_set_timing.restype = ci
         L.ifgf_destroy.argtypes = [vp]
         L.ifgf_destroy.restype = None
         L.ifgf_last_error.restype = C.c_char_p
-        for name in ("ifgf_plan", "ifgf_apply", "ifgf_plan_counts", "ifgf_plan_table", "ifgf_stats"):
+        L.nmuller_default_params.argtypes = [C.POINTER(NMullerParams)]
+        L.nmuller_default_params.restype = None
+        L.nmuller_plan.argtypes = [C.POINTER(vp), C.POINTER(NMullerParams), vp, vp, vp, dbl,
+                                   C.POINTER(Options)]
+        L.nmuller_apply.argtypes = [vp, vp, ci, vp, vp]
+        L.nmuller_rhs.argtypes = [vp, vp, vp, ci, vp, vp]
+        L.nmuller_geometry.argtypes = [vp, ci, vp, i64]
+        L.nmuller_corrections.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
+        L.nmuller_ifgf.argtypes = [vp]
+        L.nmuller_ifgf.restype = vp
+        L.nmuller_destroy.argtypes = [vp]
+        L.nmuller_destroy.restype = None
+        for name in ("ifgf_plan", "ifgf_apply", "ifgf_plan_counts", "ifgf_plan_table", "ifgf_stats",
+                     "nmuller_plan", "nmuller_apply", "nmuller_rhs", "nmuller_geometry",
+                     "nmuller_corrections"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -143,6 +165,10 @@ def ifgf_stats(plan):
     return json.loads(buf.value.decode())
 
 
+def ifgf_set_timing(plan, on):
+    _check(lib().ifgf_set_timing(plan, int(bool(on))), "ifgf_set_timing")
+
+
 def ifgf_destroy(plan):
     if plan:
         lib().ifgf_destroy(plan)
@@ -177,9 +203,120 @@ class IFGFPlan:
     def stats(self):
         return ifgf_stats(self.handle)
 
+    def set_timing(self, on=True):
+        ifgf_set_timing(self.handle, on)
+
     def close(self):
         if self.handle:
             ifgf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nmuller_plan(P, Nc, points, du, dv, eps_e, eps_i, mu_e=1.0, mu_i=1.0, omega=2 * np.pi,
+                 tol=1e-4, delta_factor=0.0, nbeta=0, d_cov=0, **opts):
+    """Build an N-Mueller operator plan; returns an opaque handle (int)."""
+    n = P * Nc * Nc
+    x = _host_f64(points, (n, 3))
+    a = _host_f64(du, (n, 3))
+    b = _host_f64(dv, (n, 3))
+    prm = NMullerParams()
+    lib().nmuller_default_params(C.byref(prm))
+    prm.P, prm.Nc = int(P), int(Nc)
+    prm.eps_e, prm.eps_i, prm.mu_e, prm.mu_i, prm.omega = eps_e, eps_i, mu_e, mu_i, omega
+    prm.delta_factor, prm.nbeta = float(delta_factor), int(nbeta)
+    if d_cov:
+        prm.d_cov = int(d_cov)
+    o = default_options()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    h = C.c_void_p()
+    _check(lib().nmuller_plan(C.byref(h), C.byref(prm), x.ctypes.data, a.ctypes.data,
+                              b.ctypes.data, float(tol), C.byref(o)), "nmuller_plan")
+    return h.value
+
+
+def nmuller_apply(nm, y, nrhs, Ay, stream=None):
+    """y, Ay: device [nrhs][4][n] complex128."""
+    _check(lib().nmuller_apply(nm, y.data_ptr(), int(nrhs), Ay.data_ptr(), _stream_ptr(stream)),
+           "nmuller_apply")
+
+
+def nmuller_rhs(nm, E, H, nrhs, b, stream=None):
+    """E, H: device [nrhs][n][3] complex128; b: device [nrhs][4][n] complex128."""
+    _check(lib().nmuller_rhs(nm, E.data_ptr(), H.data_ptr(), int(nrhs), b.data_ptr(),
+                             _stream_ptr(stream)), "nmuller_rhs")
+
+
+def nmuller_geometry(nm, which, n):
+    shape = (n,) if which in (1, 4) else (n, 3)
+    out = np.zeros(shape)
+    _check(lib().nmuller_geometry(nm, int(which), out.ctypes.data, out.size), "nmuller_geometry")
+    return out
+
+
+def nmuller_corrections(nm, n, nc, values=True):
+    npairs = C.c_int64()
+    _check(lib().nmuller_corrections(nm, C.byref(npairs), None, None, None), "nmuller_corrections")
+    ro = np.zeros(n + 1, dtype=np.int64)
+    pp = np.zeros(npairs.value, dtype=np.int32)
+    vals = np.zeros((npairs.value, 4, nc * nc, 2)) if values else None
+    _check(lib().nmuller_corrections(nm, C.byref(npairs), ro.ctypes.data, pp.ctypes.data,
+                                     vals.ctypes.data if values else None), "nmuller_corrections")
+    if values:
+        vals = vals[..., 0] + 1j * vals[..., 1]
+    return ro, pp, vals
+
+
+def nmuller_destroy(nm):
+    if nm:
+        lib().nmuller_destroy(nm)
+
+
+class NMullerOperator:
+    """Owning wrapper around an N-Mueller plan."""
+
+    def __init__(self, surface, eps_e, eps_i, mu_e=1.0, mu_i=1.0, omega=2 * np.pi, tol=1e-4,
+                 **kw):
+        self.n = surface.n
+        self.P, self.Nc = surface.P, surface.nc
+        self.max_nrhs = int(kw.get("max_nrhs", 1))
+        self.handle = nmuller_plan(surface.P, surface.nc, surface.x, surface.du, surface.dv,
+                                   eps_e, eps_i, mu_e, mu_i, omega, tol, **kw)
+
+    def apply(self, y, out=None, stream=None):
+        import torch
+        if y.dtype != torch.complex128 or not y.is_contiguous() or tuple(y.shape[1:]) != (4, self.n):
+            raise ValueError(f"y must be a contiguous complex128 tensor [nrhs, 4, {self.n}]")
+        if out is None:
+            out = torch.empty_like(y)
+        nmuller_apply(self.handle, y, y.shape[0], out, stream)
+        return out
+
+    def rhs(self, E, H, stream=None):
+        import torch
+        nrhs = E.shape[0]
+        b = torch.empty((nrhs, 4, self.n), dtype=torch.complex128, device=E.device)
+        nmuller_rhs(self.handle, E.contiguous(), H.contiguous(), nrhs, b, stream)
+        return b
+
+    def geometry(self, which):
+        return nmuller_geometry(self.handle, which, self.n)
+
+    def corrections(self, values=True):
+        return nmuller_corrections(self.handle, self.n, self.Nc, values)
+
+    def ifgf_handle(self):
+        return lib().nmuller_ifgf(self.handle)
+
+    def close(self):
+        if self.handle:
+            nmuller_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -14,6 +14,59 @@
 
 using namespace ifgf;
 
+// Optional per-kernel timing: HIP events recorded around each launch on the
+// caller's stream; durations are collected when the statistics are read.
+struct PhaseTimer {
+  bool on = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+    double units;
+  };
+  std::vector<Rec> pending;
+  struct Acc {
+    int64_t launches = 0;
+    double ms = 0.0, units = 0.0;
+  };
+  std::vector<std::pair<std::string, Acc>> acc;
+  hipEvent_t begin(hipStream_t st) {
+    hipEvent_t e = nullptr;
+    if (on && hipEventCreate(&e) == hipSuccess) (void)hipEventRecord(e, st);
+    return e;
+  }
+  void end(const char* name, hipEvent_t a, hipStream_t st, double units) {
+    if (!on || !a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    (void)hipEventRecord(b, st);
+    pending.push_back({name, a, b, units});
+  }
+  void collect() {
+    for (auto& r : pending) {
+      float ms = 0.f;
+      (void)hipEventSynchronize(r.b);
+      (void)hipEventElapsedTime(&ms, r.a, r.b);
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+      Acc* a = nullptr;
+      for (auto& kv : acc)
+        if (kv.first == r.name) a = &kv.second;
+      if (!a) {
+        acc.push_back({r.name, Acc()});
+        a = &acc.back().second;
+      }
+      a->launches += 1;
+      a->ms += ms;
+      a->units += r.units;
+    }
+    pending.clear();
+  }
+  void reset() {
+    collect();
+    acc.clear();
+  }
+};
+
 struct ifgf_plan_s {
   HostPlan host;
   ifgf_options opt;
@@ -32,6 +85,7 @@ struct ifgf_plan_s {
   double2* d_out_s = nullptr;  // [n][28]
   double2* d_vals[2] = {nullptr, nullptr};
   int64_t max_slots = 0;
+  PhaseTimer timer;
 };
 
 namespace {
@@ -246,34 +300,47 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
   const HostPlan& H = p->host;
   const int64_t n = H.n;
   const double k0 = H.k[0], k1 = H.k[1];
+  PhaseTimer& T = p->timer;
   for (int r = 0; r < nrhs; ++r) {
     const double2* dens = static_cast<const double2*>(densities) + (int64_t)r * kNS * n;
     double2* o = static_cast<double2*>(out) + (int64_t)r * kOut * n;
     hipError_t e;
+    hipEvent_t ev = T.begin(st);
     if ((e = launch_gather_weighted(dens, p->d_perm, p->d_w, n, p->d_a, st)) != hipSuccess)
       return set_hip_error(e, "gather");
+    T.end("gather", ev, st, (double)n);
+    ev = T.begin(st);
     if ((e = launch_near(p->lev[H.D], p->d_leaf_of_point, p->d_xs, p->d_nrm, p->d_a, n, k0, k1,
                          p->d_out_s, st)) != hipSuccess)
       return set_hip_error(e, "near");
+    T.end("near", ev, st, (double)H.near_pairs);
     if (H.D >= 3) {
       int cur = 0;
+      ev = T.begin(st);
       if ((e = launch_leaf(p->lev[H.D], p->ic, p->d_xs, p->d_a, k0, k1, p->d_vals[cur], st)) !=
           hipSuccess)
         return set_hip_error(e, "leaf");
+      T.end("leaf", ev, st, (double)H.leaf_pairs);
       for (int d = H.D; d >= 3; --d) {
+        ev = T.begin(st);
         if ((e = launch_targets(p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1, p->d_vals[cur],
                                 p->d_out_s, st)) != hipSuccess)
           return set_hip_error(e, "targets");
+        T.end("targets", ev, st, (double)H.lev[d].tp_off.back());
         if (d > 3) {
+          ev = T.begin(st);
           if ((e = launch_propagate(p->lev[d], p->lev[d - 1], p->ic, k0, k1, p->d_vals[cur],
                                     p->d_vals[cur ^ 1], st)) != hipSuccess)
             return set_hip_error(e, "propagate");
+          T.end("propagate", ev, st, (double)H.lev[d - 1].pp_off.back());
           cur ^= 1;
         }
       }
     }
+    ev = T.begin(st);
     if ((e = launch_scatter_out(p->d_out_s, p->d_perm, n, o, st)) != hipSuccess)
       return set_hip_error(e, "scatter");
+    T.end("scatter", ev, st, (double)n);
   }
   return IFGF_OK;
 }
@@ -344,13 +411,36 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
          std::to_string(L.nb) + ",\"ns\":" + std::to_string(L.ns) + ",\"na\":" +
          std::to_string(L.na) + ",\"slots\":" + std::to_string(L.nslots) + "}";
   }
-  s += "]}";
+  s += "],\"timing\":{";
+  p->timer.collect();
+  bool first = true;
+  for (auto& kv : p->timer.acc) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s\"%s\":{\"launches\":%lld,\"ms\":%.6f,\"units\":%.1f}",
+                  first ? "" : ",", kv.first.c_str(), (long long)kv.second.launches, kv.second.ms,
+                  kv.second.units);
+    s += buf;
+    first = false;
+  }
+  s += "}}";
   if (s.size() + 1 > cap) return set_error(IFGF_EINVAL, "json buffer too small");
   std::memcpy(json, s.c_str(), s.size() + 1);
   return IFGF_OK;
 }
 
-void ifgf_destroy(ifgf_plan_t p) { delete p; }
+int ifgf_set_timing(ifgf_plan_t p, int on) {
+  clear_error();
+  if (!p) return set_error(IFGF_EINVAL, "plan is NULL");
+  p->timer.reset();
+  p->timer.on = on != 0;
+  return IFGF_OK;
+}
+
+void ifgf_destroy(ifgf_plan_t p) {
+  if (!p) return;
+  p->timer.reset();
+  delete p;
+}
 
 const char* ifgf_last_error(void) { return last_error_cstr(); }
 
