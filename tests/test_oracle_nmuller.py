@@ -36,8 +36,8 @@ def test_mie_series_self_consistent():
     Es, Hs = M.fields(X, "sca")
     assert np.max(np.abs(np.cross(X, Ein - Ea - Es))) < 1e-12
     assert np.max(np.abs(np.cross(X, Hin - Ha - Hs))) < 1e-12
-    small = mie.MieSphere(0.01, w, 1.5 * w, w)
-    E, _ = small.fields(0.005 * X, "int")
+    small = mie.MieSphere(1e-4, w, 1.5 * w, w)
+    E, _ = small.fields(5e-5 * X, "int")
     assert np.max(np.abs(E[:, 0] - 3 / (2.25 + 2))) < 5e-3
 
 
