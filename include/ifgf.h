@@ -185,6 +185,27 @@ int nmuller_geometry(nmuller_t nm, int which, double* buf, int64_t cap);
 int nmuller_corrections(nmuller_t nm, int64_t* npairs, int64_t* row_off,
                         int32_t* pair_patch, double* vals);
 
+/* Per right-hand side outcome of nmuller_solve.                             */
+typedef struct {
+  int iters;              /* matrix-vector products in the Arnoldi process     */
+  int converged;          /* 1 when true_relres <= rtol                        */
+  double true_relres;     /* ||b - A y|| / ||b|| from a final FP64 matvec      */
+  double arnoldi_relres;  /* GMRES residual estimate at exit                   */
+  double seconds;         /* host wall time of this right-hand side            */
+} ifgf_solve_info;
+
+/* Solve A y = b by GMRES (Sec. III-A eq. lin_system): Arnoldi in FP64 with
+ * Gram-Schmidt applied twice, Givens rotations, stop when the residual
+ * estimate reaches rtol (the paper uses 1e-4), restart after `restart`
+ * iterations (0 = none), at most maxit matvecs per right-hand side.
+ *  rhs  device [nrhs][4][n] complex FP64
+ *  y    device [nrhs][4][n]: initial guess if use_x0, else overwritten from 0
+ *  info host [nrhs] (may be NULL)
+ * Returns IFGF_WNOCONV (> 0) if some true residual exceeds rtol; the best
+ * iterate is still returned.  Synchronises the stream once per iteration.  */
+int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, int use_x0, double rtol,
+                  int maxit, int restart, ifgf_solve_info* info, void* stream);
+
 /* The IFGF plan used by the operator (owned by nm).                         */
 ifgf_plan_t nmuller_ifgf(nmuller_t nm);
 

@@ -41,7 +41,8 @@ class NMuller:
     def __init__(self, surf: PatchSurface, eps_e, eps_i, mu_e=1.0, mu_i=1.0,
                  omega=2 * math.pi, sing: singular.Params | None = None, corrections=None,
                  patches=None):
-        """patches: evaluate A y only on the rows of these patches (None = all)."""
+        """patches: evaluate A y only on the rows of these patches (None = all).
+        corrections: precomputed correction matrices ({} for geometry-only use)."""
         self.s = surf
         nq = surf.nc * surf.nc
         self.rows = (np.arange(surf.N) if patches is None else

@@ -36,6 +36,11 @@ class NMullerParams(C.Structure):
                 ("delta_factor", C.c_double), ("nbeta", C.c_int), ("d_cov", C.c_int)]
 
 
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("true_relres", C.c_double),
+                ("arnoldi_relres", C.c_double), ("seconds", C.c_double)]
+
+
 _lib = None
 
 
@@ -71,6 +76,8 @@ def lib():
         L.nmuller_rhs.argtypes = [vp, vp, vp, ci, vp, vp]
         L.nmuller_geometry.argtypes = [vp, ci, vp, i64]
         L.nmuller_corrections.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
+        L.nmuller_solve.argtypes = [vp, vp, ci, vp, ci, dbl, ci, ci, C.POINTER(SolveInfo), vp]
+        L.nmuller_solve.restype = ci
         L.nmuller_ifgf.argtypes = [vp]
         L.nmuller_ifgf.restype = vp
         L.nmuller_destroy.argtypes = [vp]
@@ -273,6 +280,16 @@ def nmuller_corrections(nm, n, nc, values=True):
     return ro, pp, vals
 
 
+def nmuller_solve(nm, rhs, nrhs, y, use_x0=False, rtol=1e-4, maxit=500, restart=0, stream=None):
+    """GMRES; rhs, y device [nrhs][4][n] complex128.  Returns a list of dicts."""
+    info = (SolveInfo * int(nrhs))()
+    _check(lib().nmuller_solve(nm, rhs.data_ptr(), int(nrhs), y.data_ptr(), int(bool(use_x0)),
+                               float(rtol), int(maxit), int(restart), info, _stream_ptr(stream)),
+           "nmuller_solve")
+    return [{"iters": i.iters, "converged": bool(i.converged), "true_relres": i.true_relres,
+             "arnoldi_relres": i.arnoldi_relres, "seconds": i.seconds} for i in info]
+
+
 def nmuller_destroy(nm):
     if nm:
         lib().nmuller_destroy(nm)
@@ -304,6 +321,15 @@ class NMullerOperator:
         b = torch.empty((nrhs, 4, self.n), dtype=torch.complex128, device=E.device)
         nmuller_rhs(self.handle, E.contiguous(), H.contiguous(), nrhs, b, stream)
         return b
+
+    def solve(self, b, y=None, rtol=1e-4, maxit=500, restart=0, stream=None):
+        import torch
+        use_x0 = y is not None
+        if y is None:
+            y = torch.empty_like(b)
+        info = nmuller_solve(self.handle, b.contiguous(), b.shape[0], y, use_x0, rtol, maxit, restart,
+                             stream)
+        return y, info
 
     def geometry(self, which):
         return nmuller_geometry(self.handle, which, self.n)

@@ -1,0 +1,64 @@
+"""GPU GMRES solve of the N-Mueller system: true residual, Mie series, and the
+paper's Table II first row (N = 3456, k_i = 3 pi, Nc = 12)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mie, nmuller, surface
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_table2_row1.json")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _solve_sphere(npf, nc, Ps, Pa, restart=0):
+    from paper_2408_02274_amd import NMullerOperator
+    s = synth.cube_sphere(npf, nc, 1.0)
+    surf = surface.PatchSurface(s.P, s.nc, s.x, s.du, s.dv)
+    nm_o = nmuller.NMuller(surf, 1.0, 2.25, corrections={})    # geometry only
+    E, H = nm_o.incident_plane_wave([0, 0, 1.0], [1.0, 0, 0])
+    op = NMullerOperator(s, 1.0, 2.25, tol=1e-3, Ps=Ps, Pa=Pa)
+    b = op.rhs(torch.from_numpy(E[None]).to("cuda"), torch.from_numpy(H[None]).to("cuda"))
+    y, info = op.solve(b, rtol=1e-4, maxit=300, restart=restart)
+    r = b - op.apply(y)
+    rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    yh = y.cpu().numpy()[0]
+    op.close()
+    pts = synth.fibonacci_sphere(1000, 0.7)
+    Ec, _ = nmuller.interior_field(nm_o, yh, pts)
+    Em, _ = mie.MieSphere(1.0, nm_o.ke, nm_o.ki, nm_o.omega).fields(pts, "int")
+    return info[0], rel, float(np.linalg.norm(Ec - Em) / np.linalg.norm(Em))
+
+
+def test_solve_config1_sphere():
+    _say("[gpu] nmuller_solve config1 Ps=5 Pa=5")
+    info, rel, err = _solve_sphere(2, 8, 5, 5)
+    _say(info, rel, err)
+    assert info["converged"] and info["true_relres"] <= 1e-4
+    assert abs(rel - info["true_relres"]) < 1e-8
+    assert err < 1.5e-2
+
+
+def test_solve_restarted():
+    _say("[gpu] nmuller_solve config1 restart=8")
+    info, rel, err = _solve_sphere(2, 8, 5, 5, restart=8)
+    assert info["converged"] and rel <= 1e-4 and err < 1.5e-2
+
+
+def test_table2_row1_against_paper():
+    gold = json.load(open(GOLD))
+    _say("[gpu] nmuller_solve Table II row 1: 24 patches x 12 x 12, k_i = 3 pi")
+    info, rel, err = _solve_sphere(2, 12, 5, 5)
+    _say(info, rel, err)
+    assert info["converged"] and rel <= 1e-4
+    # the paper: 27 iterations and 9.71e-5 with IFGF, 26 and 8.8e-5 without
+    assert abs(info["iters"] - gold["iterations_cbie_ifgf"]) <= 0.25 * gold["iterations_cbie_ifgf"]
+    assert err < 2.5 * gold["error_cbie_ifgf"]
