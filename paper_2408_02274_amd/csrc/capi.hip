@@ -88,6 +88,13 @@ struct ifgf_plan_s {
   PhaseTimer timer;
 };
 
+namespace ifgf {
+hipEvent_t timer_begin(ifgf_plan_s* p, hipStream_t st) { return p ? p->timer.begin(st) : nullptr; }
+void timer_end(ifgf_plan_s* p, const char* name, hipEvent_t ev, hipStream_t st, double units) {
+  if (p) p->timer.end(name, ev, st, units);
+}
+}  // namespace ifgf
+
 namespace {
 
 int tol_to_orders(double tol, int* Ps, int* Pa) {

@@ -57,3 +57,10 @@ hipError_t launch_scatter_out(const double2* out_s, const int64_t* perm, int64_t
                               double2* out, hipStream_t st);
 
 }  // namespace ifgf
+
+// Per-kernel timing hooks of a plan (no-ops unless ifgf_set_timing(plan, 1)).
+struct ifgf_plan_s;
+namespace ifgf {
+hipEvent_t timer_begin(ifgf_plan_s* p, hipStream_t st);
+void timer_end(ifgf_plan_s* p, const char* name, hipEvent_t ev, hipStream_t st, double units);
+}  // namespace ifgf

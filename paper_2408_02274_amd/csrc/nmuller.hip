@@ -389,18 +389,25 @@ int nmuller_apply(nmuller_t nm, const void* y, int nrhs, void* Ay, void* stream)
   const int nq = nm->gd.nc * nm->gd.nc;
   const int bs = ((nq + 63) / 64) * 64;
   const double2* yy = static_cast<const double2*>(y);
+  const int64_t npairs = nm->cor.row_off.back();
+  hipEvent_t ev = timer_begin(nm->ifgf, st);
   hipLaunchKernelGGL(k_pre, dim3(nm->prm.P, nrhs), dim3(bs), 0, st, nm->gd, yy, nm->d_phi);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_hip_error(e, "nmuller pre");
+  timer_end(nm->ifgf, "nm_pre", ev, st, (double)n * nrhs);
   int rc = ifgf_apply(nm->ifgf, nm->d_phi, nrhs, nm->d_sd, stream);
   if (rc) return rc;
   const int wpb = 4;   // wavefronts (targets) per block
+  ev = timer_begin(nm->ifgf, st);
   hipLaunchKernelGGL(k_correct, dim3((unsigned)((n + wpb - 1) / wpb), nrhs), dim3(64 * wpb), 0, st,
                      nm->d_row_off, nm->d_pair_patch, nm->d_vals, nq, n, nm->d_phi, nm->d_sd, nrhs);
   if ((e = hipGetLastError()) != hipSuccess) return set_hip_error(e, "nmuller correction");
+  timer_end(nm->ifgf, "nm_correct", ev, st, (double)npairs * nq * nrhs);
+  ev = timer_begin(nm->ifgf, st);
   hipLaunchKernelGGL(k_post, dim3(nm->prm.P, nrhs), dim3(bs), 0, st, nm->gd, nm->mat, yy, nm->d_sd,
                      static_cast<double2*>(Ay));
   if ((e = hipGetLastError()) != hipSuccess) return set_hip_error(e, "nmuller post");
+  timer_end(nm->ifgf, "nm_post", ev, st, (double)n * nrhs);
   return IFGF_OK;
 }
 
