@@ -9,6 +9,7 @@
 
 #include "../../include/ifgf.h"
 #include "device.hpp"
+#include "ifgf_mfma.hpp"
 #include "plan.hpp"
 #include "util.hpp"
 
@@ -86,6 +87,11 @@ struct ifgf_plan_s {
   double2* d_vals[2] = {nullptr, nullptr};
   int64_t max_slots = 0;
   PhaseTimer timer;
+  // matrix-core path (Pa = 5): K-slot cone layout, FP32 or FP64 cone data
+  bool mfma = false;
+  bool fp32 = false;
+  void* d_af = nullptr;                 // FP32 weighted densities [n][16]
+  std::vector<PropGroups> groups;       // groups[d]: propagation into level d
 };
 
 namespace ifgf {
@@ -247,6 +253,15 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     delete p;
     return rc;
   }
+  p->mfma = mfma_path_supported(opt.Ps, opt.Pa);
+  p->fp32 = opt.precision == IFGF_FP32;
+  if (p->fp32 && !p->mfma) {
+    delete p;
+    return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 and 3 <= Ps <= 6");
+  }
+  if (p->mfma)
+    for (int d = 1; d <= H.D; ++d) std::vector<int32_t>().swap(H.lev[d].pp_slot);
+  p->groups.assign(H.D + 1, PropGroups());
   p->lev.assign(H.D + 1, DevLevel());
   for (int d = 1; d <= H.D; ++d) {
     HostLevel& L = H.lev[d];
@@ -272,6 +287,29 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
         return rc;
       }
     }
+    if (p->mfma && !L.pg_off.empty()) {
+      PropGroups& PG = p->groups[d];
+      int64_t *o = nullptr, *st = nullptr;
+      int32_t *sl = nullptr, *cb = nullptr, *cn = nullptr;
+      uint8_t* pt = nullptr;
+      if ((rc = upload(ar, L.pg_off, &o)) || (rc = upload(ar, L.pg_start, &st)) ||
+          (rc = upload(ar, L.pg_slot, &sl)) || (rc = upload(ar, L.pg_cbox, &cb)) ||
+          (rc = upload(ar, L.pg_count, &cn)) || (rc = upload(ar, L.pg_pts, &pt))) {
+        delete p;
+        return rc;
+      }
+      PG.off = o;
+      PG.start = st;
+      PG.slot = sl;
+      PG.cbox = cb;
+      PG.count = cn;
+      PG.pts = pt;
+      std::vector<int64_t>().swap(L.pg_start);
+      std::vector<int32_t>().swap(L.pg_slot);
+      std::vector<int32_t>().swap(L.pg_cbox);
+      std::vector<int32_t>().swap(L.pg_count);
+      std::vector<uint8_t>().swap(L.pg_pts);
+    }
     if (d >= 3) p->max_slots = std::max(p->max_slots, L.nslots);
     // the host copies of the large pair tables are no longer needed
     std::vector<int32_t>().swap(L.tp_slot);
@@ -283,8 +321,17 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     delete p;
     return set_error(IFGF_ENOMEM, "device workspace allocation failed");
   }
+  if (p->fp32) {
+    p->d_af = ar.alloc(sizeof(float) * 16 * (size_t)n);
+    if (!p->d_af) {
+      delete p;
+      return set_error(IFGF_ENOMEM, "device workspace allocation failed");
+    }
+  }
   if (p->max_slots > 0) {
-    size_t vb = sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
+    size_t vb = p->mfma ? (p->fp32 ? sizeof(float) : sizeof(double)) * (size_t)p->max_slots *
+                              kslot_rows(opt.Ps) * 32
+                        : sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
     p->d_vals[0] = static_cast<double2*>(ar.alloc(vb));
     p->d_vals[1] = static_cast<double2*>(ar.alloc(vb));
     if (!p->d_vals[0] || !p->d_vals[1]) {
@@ -321,7 +368,35 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
                          p->d_out_s, st)) != hipSuccess)
       return set_hip_error(e, "near");
     T.end("near", ev, st, (double)H.near_pairs);
-    if (H.D >= 3) {
+    if (H.D >= 3 && p->mfma) {
+      int cur = 0;
+      const void* av = p->d_a;
+      if (p->fp32) {
+        if ((e = mf_gather(true, dens, p->d_perm, p->d_w, n, p->d_af, st)) != hipSuccess)
+          return set_hip_error(e, "gather fp32");
+        av = p->d_af;
+      }
+      ev = T.begin(st);
+      if ((e = mf_leaf(p->fp32, H.Ps, p->lev[H.D], p->ic, p->d_xs, av, k0, k1, p->d_vals[cur], st)) !=
+          hipSuccess)
+        return set_hip_error(e, "leaf");
+      T.end("leaf", ev, st, (double)H.leaf_pairs);
+      for (int d = H.D; d >= 3; --d) {
+        ev = T.begin(st);
+        if ((e = mf_targets(p->fp32, H.Ps, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1, p->d_vals[cur],
+                            p->d_out_s, st)) != hipSuccess)
+          return set_hip_error(e, "targets");
+        T.end("targets", ev, st, (double)H.lev[d].tp_off.back());
+        if (d > 3) {
+          ev = T.begin(st);
+          if ((e = mf_propagate(p->fp32, H.Ps, p->lev[d], p->lev[d - 1], p->ic, p->groups[d - 1], k0, k1,
+                                p->d_vals[cur], p->d_vals[cur ^ 1], st)) != hipSuccess)
+            return set_hip_error(e, "propagate");
+          T.end("propagate", ev, st, (double)H.lev[d - 1].pp_off.back());
+          cur ^= 1;
+        }
+      }
+    } else if (H.D >= 3) {
       int cur = 0;
       ev = T.begin(st);
       if ((e = launch_leaf(p->lev[H.D], p->ic, p->d_xs, p->d_a, k0, k1, p->d_vals[cur], st)) !=

@@ -1,0 +1,570 @@
+// IFGF apply kernels on the matrix cores (MFMA 16x16x4, FP32 or FP64).
+//
+// Paper: Sec. III-G algorithm steps 2b (leaf cone values), 3a (interpolation
+// onto cousin points times the centred factor, plus its normal derivative)
+// and 3b (interpolation onto parent interpolation points times the
+// re-centring factor G(X, x_child) / G(X, x_parent), summed over children).
+//
+// Cone data layout ("K-slot" order, Pa = 5).  A cone with Ps x 5 x 5 nodes
+// (a, b, c) -> point p = 5 (5 a + b) + c is stored as K = 4 * KS rows with
+// KS = nab + ceil(nab / 4), nab = 5 Ps:
+//   c < 4 : row 4 * ab + c           (ab = 5 a + b)
+//   c = 4 : row 4 * nab + ab
+// remaining rows are zero padding.  A row holds 32 reals: the real parts of
+// the 16 complex columns (column = 8 * kernel + density) then their imaginary
+// parts.  With this order the MFMA lane group g = lane / 16 always supplies
+// the phi-node c = g (first nab k-steps) so the interpolation weight of a
+// lane is one product of per-point Lagrange factors.
+//
+// The interpolant is the tensor Chebyshev interpolant of Sec. III-F in
+// Lagrange form on the same nodes (identical polynomial).  Geometry is
+// evaluated in cone-centred coordinates so that FP32 keeps relative accuracy:
+// phases use r_child - r_parent = (|d|^2 - 2 Y.d) / (r_child + r_parent).
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "ifgf_mfma.hpp"
+
+namespace ifgf {
+
+namespace {
+
+constexpr double kPiD = 3.141592653589793;
+constexpr double kInv4PiD = 0.07957747154594767;
+constexpr double kEtaD = 0.5773502691896257;
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <class T> struct MF;
+template <> struct MF<float> {
+  using acc = f4v;
+  __device__ static acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output row of element r held by lane l
+  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct MF<double> {
+  using acc = d4v;
+  __device__ static acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+template <class T> __device__ __forceinline__ void tsincos(T x, T* s, T* c);
+template <> __device__ __forceinline__ void tsincos<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+template <> __device__ __forceinline__ void tsincos<double>(double x, double* s, double* c) { sincos(x, s, c); }
+template <class T> __device__ __forceinline__ T tacos(T x);
+template <> __device__ __forceinline__ float tacos<float>(float x) { return acosf(x); }
+template <> __device__ __forceinline__ double tacos<double>(double x) { return acos(x); }
+template <class T> __device__ __forceinline__ T tatan2(T y, T x);
+template <> __device__ __forceinline__ float tatan2<float>(float y, float x) { return atan2f(y, x); }
+template <> __device__ __forceinline__ double tatan2<double>(double y, double x) { return atan2(y, x); }
+template <class T> __device__ __forceinline__ T tsqrt(T x);
+template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
+
+// Lagrange basis on P Chebyshev nodes x with inverse denominators w
+template <int P, class T>
+__device__ __forceinline__ void lag(const double* x, const double* w, T u, T* L) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    T p = (T)w[j];
+#pragma unroll
+    for (int m = 0; m < P; ++m)
+      if (m != j) p *= (u - (T)x[m]);
+    L[j] = p;
+  }
+}
+template <int P, class T>
+__device__ __forceinline__ void lag_d(const double* x, const double* w, T u, T* dL) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    T acc = 0;
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      if (m == j) continue;
+      T p = 1;
+#pragma unroll
+      for (int l = 0; l < P; ++l)
+        if (l != j && l != m) p *= (u - (T)x[l]);
+      acc += p;
+    }
+    dL[j] = acc * (T)w[j];
+  }
+}
+
+// node (s, theta, phi) of point p of cone `cone` and the unit direction
+template <int PS, class T>
+__device__ __forceinline__ void cone_node(int ns, int na, int cone, int p, const InterpC& ic, T* s,
+                                          T* ux, T* uy, T* uz) {
+  const int ip = cone % (2 * na);
+  const int it = (cone / (2 * na)) % na;
+  const int is = cone / (2 * na * na);
+  const int c = p % 5, b = (p / 5) % 5, a = p / 25;
+  const double ds = kEtaD / ns, da = kPiD / na;
+  *s = (T)((is + 0.5) * ds + 0.5 * ds * ic.xs[a]);
+  T t = (T)((it + 0.5) * da + 0.5 * da * ic.xa[b]);
+  T f = (T)((ip + 0.5) * da + 0.5 * da * ic.xa[c]);
+  T st, ct, sp, cp;
+  tsincos<T>(t, &st, &ct);
+  tsincos<T>(f, &sp, &cp);
+  *ux = st * cp;
+  *uy = st * sp;
+  *uz = ct;
+}
+
+// local coordinates of offset (zx, zy, zz) in cone `cone` (ns, na)
+template <class T>
+__device__ __forceinline__ void local3(T zx, T zy, T zz, T h, int ns, int na, int cone, T* r, T* us,
+                                       T* ut, T* up, T* th, T* ph) {
+  *r = tsqrt<T>(zx * zx + zy * zy + zz * zz);
+  T s = h / *r;
+  T ct = zz / *r;
+  ct = ct > (T)1 ? (T)1 : (ct < (T)-1 ? (T)-1 : ct);
+  *th = tacos<T>(ct);
+  *ph = tatan2<T>(zy, zx);
+  if (*ph < (T)0) *ph += (T)(2.0 * kPiD);
+  const int ip = cone % (2 * na);
+  const int it = (cone / (2 * na)) % na;
+  const int is = cone / (2 * na * na);
+  const T ds = (T)(kEtaD / ns), da = (T)(kPiD / na);
+  *us = (s - ((T)is + (T)0.5) * ds) / ((T)0.5 * ds);
+  *ut = (*th - ((T)it + (T)0.5) * da) / ((T)0.5 * da);
+  *up = (*ph - ((T)ip + (T)0.5) * da) / ((T)0.5 * da);
+}
+
+__device__ __forceinline__ int point_of_row(int row, int nab) {
+  if (row < 4 * nab) return 5 * (row >> 2) + (row & 3);
+  int m = row - 4 * nab;
+  return m < nab ? 5 * m + 4 : -1;
+}
+__device__ __forceinline__ int row_of_point(int p, int nab) {
+  int c = p % 5, ab = p / 5;
+  return c < 4 ? 4 * ab + c : 4 * nab + ab;
+}
+
+// ---------------------------------------------------------------------------
+// weighted densities in sorted order: a[i][m] = w_i phi_m(perm[i])
+template <class T>
+__global__ void k_gather(const double2* __restrict__ dens, const int64_t* __restrict__ perm,
+                         const double* __restrict__ w, int64_t n, T* __restrict__ a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * 8) return;
+  int64_t i = t / 8;
+  int m = (int)(t % 8);
+  double2 v = dens[(int64_t)m * n + perm[i]];
+  a[2 * t] = (T)(v.x * w[i]);
+  a[2 * t + 1] = (T)(v.y * w[i]);
+}
+
+// leaf cone values: thread per (slot, row)
+template <int PS, class T>
+__global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const double* __restrict__ xs, const T* __restrict__ a,
+                         double k0, double k1, T* __restrict__ V) {
+  constexpr int NAB = PS * 5;
+  constexpr int K = 4 * (NAB + (NAB + 3) / 4);
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.nslots * K) return;
+  int64_t q = t / K;
+  int row = (int)(t % K);
+  T* o = V + t * 32;
+  int p = point_of_row(row, NAB);
+  if (p < 0) {
+#pragma unroll
+    for (int c = 0; c < 32; ++c) o[c] = (T)0;
+    return;
+  }
+  int32_t b = L.slot_box[q];
+  const double* c = L.centers + 3 * b;
+  T s, ux, uy, uz;
+  cone_node<PS, T>(L.ns, L.na, L.slot_cone[q], p, ic, &s, &ux, &uy, &uz);
+  const T rxc = (T)L.h / s;
+  const T Yx = rxc * ux, Yy = rxc * uy, Yz = rxc * uz;
+  T acc[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) acc[m] = (T)0;
+  const T kk[2] = {(T)k0, (T)k1};
+  for (int32_t j = L.start[b]; j < L.end[b]; ++j) {
+    const T yx = (T)(xs[3 * j] - c[0]), yy = (T)(xs[3 * j + 1] - c[1]), yz = (T)(xs[3 * j + 2] - c[2]);
+    const T dx = Yx - yx, dy = Yy - yy, dz = Yz - yz;
+    const T rxy = tsqrt<T>(dx * dx + dy * dy + dz * dz);
+    const T diff = (yx * yx + yy * yy + yz * yz - (T)2 * (Yx * yx + Yy * yy + Yz * yz)) / (rxy + rxc);
+    const T ratio = rxc / rxy;
+    const T* aj = a + (int64_t)j * 16;
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      T sn, cs;
+      tsincos<T>(kk[qq] * diff, &sn, &cs);
+      const T gr = ratio * cs, gi = ratio * sn;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const T ar = aj[2 * m], ai = aj[2 * m + 1];
+        acc[qq * 8 + m] += gr * ar - gi * ai;
+        acc[16 + qq * 8 + m] += gr * ai + gi * ar;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 32; ++m) o[m] = acc[m];
+}
+
+// ---------------------------------------------------------------------------
+// propagation: one workgroup per parent cone slot, 4 wavefronts
+template <int PS, class T>
+__global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, InterpC ic, PropGroups G,
+                                                   double k0, double k1, const T* __restrict__ Vc,
+                                                   T* __restrict__ Vp) {
+  constexpr int NAB = PS * 5;
+  constexpr int KS = NAB + (NAB + 3) / 4;
+  constexpr int K = 4 * KS;
+  constexpr int NPTS = NAB * 5;
+  __shared__ T acc[NPTS][33];
+  __shared__ T fac[4][16][4];   // per wave: per tile row, factor (re, im) for both kernels
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < NPTS * 33; i += 256) (&acc[0][0])[i] = (T)0;
+  __syncthreads();
+  const int32_t pb = P.slot_box[q];
+  const int pcone = P.slot_cone[q];
+  const double* cp = P.centers + 3 * pb;
+  const int64_t g0 = G.off[q], g1 = G.off[q + 1];
+  const int r16 = lane & 15, gl = lane >> 4;
+  const T kk[2] = {(T)k0, (T)k1};
+  for (int64_t g = g0 + wave; g < g1; g += 4) {
+    const int32_t slot = G.slot[g];
+    const int32_t cb = G.cbox[g];
+    const int64_t pstart = G.start[g];
+    const int cnt = G.count[g];
+    const int ccone = C.slot_cone[slot];
+    const double* cc = C.centers + 3 * cb;
+    const T dx = (T)(cc[0] - cp[0]), dy = (T)(cc[1] - cp[1]), dz = (T)(cc[2] - cp[2]);
+    const T d2 = dx * dx + dy * dy + dz * dz;
+    const T* Vs = Vc + (int64_t)slot * K * 32;
+    for (int t0 = 0; t0 < cnt; t0 += 16) {
+      const bool valid = t0 + r16 < cnt;
+      const int p = valid ? (int)G.pts[pstart + t0 + r16] : 0;
+      // geometry of parent point p in parent-centred coordinates, then about the child
+      T s, ux, uy, uz;
+      cone_node<PS, T>(P.ns, P.na, pcone, p, ic, &s, &ux, &uy, &uz);
+      const T rp = (T)P.h / s;
+      const T Yx = rp * ux, Yy = rp * uy, Yz = rp * uz;
+      T rc, us, ut, up, th, ph;
+      local3<T>(Yx - dx, Yy - dy, Yz - dz, (T)C.h, C.ns, C.na, ccone, &rc, &us, &ut, &up, &th, &ph);
+      T Ls[PS], Lt[5], Lp[5];
+      lag<PS, T>(ic.xs, ic.ws, us, Ls);
+      lag<5, T>(ic.xa, ic.wa, ut, Lt);
+      lag<5, T>(ic.xa, ic.wa, up, Lp);
+      if (gl == 0) {
+        // re-centring factor G(X, x_child) / G(X, x_parent) = (rp / rc) exp(i k (rc - rp))
+        const T diff = (d2 - (T)2 * (Yx * dx + Yy * dy + Yz * dz)) / (rc + rp);
+        const T ratio = rp / rc;
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+          T sn, cs;
+          tsincos<T>(kk[qq] * diff, &sn, &cs);
+          fac[wave][r16][2 * qq] = ratio * cs;
+          fac[wave][r16][2 * qq + 1] = ratio * sn;
+        }
+      }
+      const T lpg = gl == 0 ? Lp[0] : gl == 1 ? Lp[1] : gl == 2 ? Lp[2] : Lp[3];
+      const T vmask = valid ? (T)1 : (T)0;
+      typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < KS; ++j) {
+        T av;
+        if (j < NAB) {
+          av = Ls[j / 5] * Lt[j % 5] * lpg;
+        } else {
+          const int m = 4 * (j - NAB) + gl;
+          const int ma = m / 5, mb = m % 5;
+          T la = (T)0, lb = (T)0;
+#pragma unroll
+          for (int z = 0; z < PS; ++z) la = (ma == z) ? Ls[z] : la;
+#pragma unroll
+          for (int z = 0; z < 5; ++z) lb = (mb == z) ? Lt[z] : lb;
+          av = m < NAB ? la * lb * Lp[4] : (T)0;
+        }
+        av *= vmask;
+        const T* vrow = Vs + (int64_t)(4 * j + gl) * 32;
+        c0 = MF<T>::mma(av, vrow[r16], c0);
+        c1 = MF<T>::mma(av, vrow[16 + r16], c1);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      // lane holds rows MF::row(lane, e), complex column r16 (kernel r16 / 8)
+      const int qq = r16 >> 3;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int orow = MF<T>::row(lane, e);
+        if (t0 + orow < cnt) {
+          const int po = (int)G.pts[pstart + t0 + orow];
+          const T fr = fac[wave][orow][2 * qq], fi = fac[wave][orow][2 * qq + 1];
+          const T vr = c0[e], vi = c1[e];
+          atomicAdd(&acc[po][r16], fr * vr - fi * vi);
+          atomicAdd(&acc[po][16 + r16], fr * vi + fi * vr);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  T* out = Vp + q * (int64_t)K * 32;
+  for (int i = tid; i < K * 32; i += 256) {
+    const int row = i >> 5, col = i & 31;
+    const int p = point_of_row(row, NAB);
+    out[i] = p >= 0 ? acc[p][col] : (T)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// interpolation onto cousin targets: thread per target, loop over its cousins
+template <int PS, class T>
+__global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const double* __restrict__ xs,
+                            const double* __restrict__ nrm, int64_t n, double k0, double k1,
+                            const T* __restrict__ V, double2* __restrict__ out_s) {
+  constexpr int NAB = PS * 5;
+  constexpr int KS = NAB + (NAB + 3) / 4;
+  constexpr int K = 4 * KS;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t e0 = L.tp_off[i], e1 = L.tp_off[i + 1];
+  if (e0 == e1) return;
+  const T nx = (T)nrm[3 * i], ny = (T)nrm[3 * i + 1], nz = (T)nrm[3 * i + 2];
+  const T kk[2] = {(T)k0, (T)k1};
+  double2* o = out_s + i * 28;
+  T Sr[2][8], Si[2][8], Dr[2][6], Di[2][6];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) { Sr[q][m] = (T)0; Si[q][m] = (T)0; }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { Dr[q][m] = (T)0; Di[q][m] = (T)0; }
+  }
+  const T ds = (T)(kEtaD / L.ns), da = (T)(kPiD / L.na);
+  for (int64_t e = e0; e < e1; ++e) {
+    const int32_t slot = L.tp_slot[e];
+    const int32_t B = L.slot_box[slot];
+    const int cone = L.slot_cone[slot];
+    const double* c = L.centers + 3 * B;
+    const T zx = (T)(xs[3 * i] - c[0]), zy = (T)(xs[3 * i + 1] - c[1]), zz = (T)(xs[3 * i + 2] - c[2]);
+    T r, us, ut, up, th, ph;
+    local3<T>(zx, zy, zz, (T)L.h, L.ns, L.na, cone, &r, &us, &ut, &up, &th, &ph);
+    T Ls[PS], Lt[5], Lp[5], dLs[PS], dLt[5], dLp[5];
+    lag<PS, T>(ic.xs, ic.ws, us, Ls);
+    lag<5, T>(ic.xa, ic.wa, ut, Lt);
+    lag<5, T>(ic.xa, ic.wa, up, Lp);
+    lag_d<PS, T>(ic.xs, ic.ws, us, dLs);
+    lag_d<5, T>(ic.xa, ic.wa, ut, dLt);
+    lag_d<5, T>(ic.xa, ic.wa, up, dLp);
+    const T rinv = (T)1 / r;
+    const T n_r = (nx * zx + ny * zy + nz * zz) * rinv;
+    T st, ct, sp, cp;
+    tsincos<T>(th, &st, &ct);
+    tsincos<T>(ph, &sp, &cp);
+    const T n_th = nx * ct * cp + ny * ct * sp - nz * st;
+    const T n_ph = -nx * sp + ny * cp;
+    T c_ph = st > (T)0 ? n_ph / (r * st) : (T)0;     // grad phi = phi-hat / (r sin theta)
+    T c_s = -((T)L.h * rinv * rinv) * n_r;           // grad s = -(h / r^2) r-hat
+    T c_t = n_th * rinv;                             // grad theta = theta-hat / r
+    c_s *= (T)2 / ds;
+    c_t *= (T)2 / da;
+    c_ph *= (T)2 / da;
+    T F[32], FD[24];
+#pragma unroll
+    for (int m = 0; m < 32; ++m) F[m] = (T)0;
+#pragma unroll
+    for (int m = 0; m < 24; ++m) FD[m] = (T)0;
+    const T* Vs = V + (int64_t)slot * K * 32;
+    // radial index a runs in a rolled loop; Ls/dLs rotate so indices stay static
+#pragma unroll 1
+    for (int a = 0; a < PS; ++a) {
+      const T la = Ls[0], dla = dLs[0];
+#pragma unroll
+      for (int z = 0; z + 1 < PS; ++z) {
+        Ls[z] = Ls[z + 1];
+        dLs[z] = dLs[z + 1];
+      }
+#pragma unroll
+      for (int b = 0; b < 5; ++b) {
+        const int ab = 5 * a + b;
+        const T lst = la * Lt[b];
+        const T dst = c_s * dla * Lt[b] + c_t * la * dLt[b];
+        const T phs = c_ph * la * Lt[b];
+        // phi index cc in a rolled loop; Lp/dLp rotate cyclically (restored after 5 steps)
+#pragma unroll 1
+        for (int cc = 0; cc < 5; ++cc) {
+          const int row = cc < 4 ? 4 * ab + cc : 4 * NAB + ab;
+          const T w = lst * Lp[0];
+          const T wd = dst * Lp[0] + phs * dLp[0];
+          {
+            const T l0 = Lp[0], d0 = dLp[0];
+#pragma unroll
+            for (int z = 0; z < 4; ++z) {
+              Lp[z] = Lp[z + 1];
+              dLp[z] = dLp[z + 1];
+            }
+            Lp[4] = l0;
+            dLp[4] = d0;
+          }
+          const T* vr = Vs + (int64_t)row * 32;
+#pragma unroll
+          for (int m = 0; m < 32; ++m) F[m] += w * vr[m];
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+              FD[q * 12 + m] += wd * vr[q * 8 + m];             // real
+              FD[q * 12 + 6 + m] += wd * vr[16 + q * 8 + m];    // imag
+            }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      T sn, cs;
+      tsincos<T>(kk[q] * r, &sn, &cs);
+      const T gr = cs * (T)kInv4PiD * rinv, gi = sn * (T)kInv4PiD * rinv;
+      const T dgr = -rinv * n_r, dgi = kk[q] * n_r;   // (i k - 1/r) n.r-hat
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const T fr = F[q * 8 + m], fi = F[16 + q * 8 + m];
+        Sr[q][m] += gr * fr - gi * fi;
+        Si[q][m] += gr * fi + gi * fr;
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const T fr = F[q * 8 + m], fi = F[16 + q * 8 + m];
+        const T tr = dgr * fr - dgi * fi + FD[q * 12 + m];
+        const T ti = dgr * fi + dgi * fr + FD[q * 12 + 6 + m];
+        Dr[q][m] += gr * tr - gi * ti;
+        Di[q][m] += gr * ti + gi * tr;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      double2 v = o[q * 14 + m];
+      o[q * 14 + m] = make_double2(v.x + (double)Sr[q][m], v.y + (double)Si[q][m]);
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double2 v = o[q * 14 + 8 + m];
+      o[q * 14 + 8 + m] = make_double2(v.x + (double)Dr[q][m], v.y + (double)Di[q][m]);
+    }
+  }
+}
+
+inline unsigned nblk(int64_t w, int bs) { return (unsigned)((w + bs - 1) / bs); }
+
+template <int PS, class T>
+hipError_t leaf_t(const DevLevel& L, const InterpC& ic, const double* xs, const void* a, double k0,
+                  double k1, void* V, hipStream_t st) {
+  constexpr int NAB = PS * 5;
+  constexpr int K = 4 * (NAB + (NAB + 3) / 4);
+  int64_t work = L.nslots * K;
+  if (work <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_leaf_k<PS, T>), dim3(nblk(work, 256)), dim3(256), 0, st, L, ic, xs,
+                     static_cast<const T*>(a), k0, k1, static_cast<T*>(V));
+  return hipGetLastError();
+}
+template <int PS, class T>
+hipError_t prop_t(const DevLevel& C, const DevLevel& P, const InterpC& ic, const PropGroups& G,
+                  double k0, double k1, const void* Vc, void* Vp, hipStream_t st) {
+  if (P.nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_prop_mfma<PS, T>), dim3((unsigned)P.nslots), dim3(256), 0, st, C, P, ic, G, k0, k1,
+                     static_cast<const T*>(Vc), static_cast<T*>(Vp));
+  return hipGetLastError();
+}
+template <int PS, class T>
+hipError_t targets_t(const DevLevel& L, const InterpC& ic, const double* xs, const double* nrm,
+                     int64_t n, double k0, double k1, const void* V, double2* out_s, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_targets_k<PS, T>), dim3(nblk(n, 64)), dim3(64), 0, st, L, ic, xs, nrm, n, k0, k1,
+                     static_cast<const T*>(V), out_s);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t dispatch_leaf(int Ps, const DevLevel& L, const InterpC& ic, const double* xs, const void* a,
+                         double k0, double k1, void* V, hipStream_t st) {
+  switch (Ps) {
+    case 3: return leaf_t<3, T>(L, ic, xs, a, k0, k1, V, st);
+    case 4: return leaf_t<4, T>(L, ic, xs, a, k0, k1, V, st);
+    case 5: return leaf_t<5, T>(L, ic, xs, a, k0, k1, V, st);
+    case 6: return leaf_t<6, T>(L, ic, xs, a, k0, k1, V, st);
+  }
+  return hipErrorInvalidValue;
+}
+template <class T>
+hipError_t dispatch_prop(int Ps, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+                         const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
+                         hipStream_t st) {
+  switch (Ps) {
+    case 3: return prop_t<3, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 4: return prop_t<4, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 5: return prop_t<5, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 6: return prop_t<6, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
+  }
+  return hipErrorInvalidValue;
+}
+template <class T>
+hipError_t dispatch_targets(int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+                            const double* nrm, int64_t n, double k0, double k1, const void* V,
+                            double2* out_s, hipStream_t st) {
+  switch (Ps) {
+    case 3: return targets_t<3, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 4: return targets_t<4, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 5: return targets_t<5, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 6: return targets_t<6, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool mfma_path_supported(int Ps, int Pa) { return Pa == 5 && Ps >= 3 && Ps <= 6; }
+
+int kslot_rows(int Ps) {
+  const int nab = 5 * Ps;
+  return 4 * (nab + (nab + 3) / 4);
+}
+
+hipError_t mf_gather(bool fp32, const double2* dens, const int64_t* perm, const double* w, int64_t n,
+                     void* a, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_gather<float>, dim3(nblk(n * 8, 256)), dim3(256), 0, st, dens, perm, w, n,
+                       static_cast<float*>(a));
+  else
+    hipLaunchKernelGGL(k_gather<double>, dim3(nblk(n * 8, 256)), dim3(256), 0, st, dens, perm, w, n,
+                       static_cast<double*>(a));
+  return hipGetLastError();
+}
+
+hipError_t mf_leaf(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+                   const void* a, double k0, double k1, void* V, hipStream_t st) {
+  return fp32 ? dispatch_leaf<float>(Ps, L, ic, xs, a, k0, k1, V, st)
+              : dispatch_leaf<double>(Ps, L, ic, xs, a, k0, k1, V, st);
+}
+
+hipError_t mf_propagate(bool fp32, int Ps, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+                        const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
+                        hipStream_t st) {
+  return fp32 ? dispatch_prop<float>(Ps, C, P, ic, G, k0, k1, Vc, Vp, st)
+              : dispatch_prop<double>(Ps, C, P, ic, G, k0, k1, Vc, Vp, st);
+}
+
+hipError_t mf_targets(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+                      const double* nrm, int64_t n, double k0, double k1, const void* V,
+                      double2* out_s, hipStream_t st) {
+  return fp32 ? dispatch_targets<float>(Ps, L, ic, xs, nrm, n, k0, k1, V, out_s, st)
+              : dispatch_targets<double>(Ps, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+}
+
+}  // namespace ifgf

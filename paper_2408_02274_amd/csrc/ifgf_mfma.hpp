@@ -1,0 +1,39 @@
+// Matrix-core IFGF path: cone data in K-slot order (Pa = 5), FP32 or FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace ifgf {
+
+// Propagation work list for one parent level: for parent cone slot q the
+// groups [off[q], off[q+1]); group g gathers the parent interpolation points
+// pts[start[g] .. start[g] + count[g]) that fall into child cone slot slot[g]
+// of child box cbox[g].
+struct PropGroups {
+  const int64_t* off = nullptr;
+  const int32_t* slot = nullptr;
+  const int32_t* cbox = nullptr;
+  const int64_t* start = nullptr;
+  const int32_t* count = nullptr;
+  const uint8_t* pts = nullptr;
+};
+
+bool mfma_path_supported(int Ps, int Pa);
+int kslot_rows(int Ps);   // rows per cone in K-slot order
+
+hipError_t mf_gather(bool fp32, const double2* dens, const int64_t* perm, const double* w, int64_t n,
+                     void* a, hipStream_t st);
+hipError_t mf_leaf(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+                   const void* a, double k0, double k1, void* V, hipStream_t st);
+hipError_t mf_propagate(bool fp32, int Ps, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+                        const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
+                        hipStream_t st);
+hipError_t mf_targets(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+                      const double* nrm, int64_t n, double k0, double k1, const void* V,
+                      double2* out_s, hipStream_t st);
+
+}  // namespace ifgf

@@ -95,6 +95,56 @@ static int find_slot(const HostLevel& L, int64_t box, int cone) {
   return (int)(L.slot_off[box] + (it - b));
 }
 
+void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts) {
+  const int64_t Q = Pl.nslots;
+  std::vector<std::vector<int32_t>> gs(Q), gc(Q), gn(Q);
+  std::vector<std::vector<uint8_t>> gp(Q);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t q = 0; q < Q; ++q) {
+    const int32_t pb = Pl.slot_box[q];
+    const int nch = Pl.child_end[pb] - Pl.child_start[pb];
+    std::vector<std::pair<int32_t, int>> tmp(npts);
+    for (int j = 0; j < nch; ++j) {
+      const int32_t* ps = &Pl.pp_slot[Pl.pp_off[q] + (int64_t)j * npts];
+      for (int k = 0; k < npts; ++k) tmp[k] = {ps[k], k};
+      std::stable_sort(tmp.begin(), tmp.end(),
+                       [](const std::pair<int32_t, int>& a, const std::pair<int32_t, int>& b) {
+                         return a.first < b.first;
+                       });
+      for (int k = 0; k < npts; ++k) {
+        if (k == 0 || tmp[k].first != tmp[k - 1].first) {
+          gs[q].push_back(tmp[k].first);
+          gc[q].push_back(Pl.child_start[pb] + j);
+          gn[q].push_back(0);
+        }
+        gn[q].back() += 1;
+        gp[q].push_back((uint8_t)tmp[k].second);
+      }
+    }
+  }
+  Pl.pg_off.assign(Q + 1, 0);
+  for (int64_t q = 0; q < Q; ++q) Pl.pg_off[q + 1] = Pl.pg_off[q] + (int64_t)gs[q].size();
+  const int64_t G = Pl.pg_off[Q];
+  Pl.pg_slot.resize(G);
+  Pl.pg_cbox.resize(G);
+  Pl.pg_count.resize(G);
+  Pl.pg_start.resize(G);
+  Pl.pg_pts.resize(Pl.pp_off[Q]);
+  for (int64_t q = 0; q < Q; ++q) {
+    int64_t g = Pl.pg_off[q];
+    int64_t st = Pl.pp_off[q];
+    std::copy(gp[q].begin(), gp[q].end(), Pl.pg_pts.begin() + st);
+    for (size_t i = 0; i < gs[q].size(); ++i, ++g) {
+      Pl.pg_slot[g] = gs[q][i];
+      Pl.pg_cbox[g] = gc[q][i];
+      Pl.pg_count[g] = gn[q][i];
+      Pl.pg_start[g] = st;
+      st += gn[q][i];
+    }
+  }
+  (void)L;
+}
+
 int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
                     const double* w, double k0, double k1, const PlanParams& pp,
                     std::string& err) {
@@ -368,6 +418,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
         }
       }
       if (bad2) { err = "internal: parent point outside relevant child cones"; return -1; }
+      if (npts <= 256) build_prop_groups(Pl, L, npts);
     }
   }
 

@@ -38,6 +38,13 @@ struct HostLevel {
   // box and interpolation point k, the child's cone slot at level d
   std::vector<int64_t> pp_off;             // [nslots(d-1)+1], stride nchild*npts
   std::vector<int32_t> pp_slot;
+  // the same pairs grouped by child cone: for parent slot q of this level the
+  // groups [pg_off[q], pg_off[q+1]); a group lists the interpolation points
+  // pg_pts[pg_start .. +pg_count) of q that lie in child cone slot pg_slot of
+  // child box pg_cbox (children in order, points ascending)
+  std::vector<int64_t> pg_off, pg_start;
+  std::vector<int32_t> pg_slot, pg_cbox, pg_count;
+  std::vector<uint8_t> pg_pts;
 };
 
 struct HostPlan {
@@ -64,6 +71,10 @@ struct PlanParams {
 int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
                     const double* w, double k0, double k1, const PlanParams& pp,
                     std::string& err);
+
+// Group the propagation pairs of parent level Pl (children at level L) by
+// child cone slot (requires npts <= 256).
+void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts);
 
 // Cone index of the offset (dx,dy,dz) from a box centre (box radius h) with
 // ns x na x 2na cones; also returns s, theta, phi.

@@ -93,3 +93,22 @@ def test_fp64_tiny_inputs_are_exact_direct_sums(npts):
     g = _gpu_apply(x, nrm, w, (3.0, 2.0), phi)[0]
     o1 = direct.regular_sums(x, nrm, w, phi[0], (3.0, 2.0))
     assert np.allclose(g, o1, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("order", [(3, 5), (5, 5)])
+def test_fp32_cone_grids_close_to_reference(case, order):
+    # FP32 cone values and interpolation (geometry in cone-centred FP32
+    # coordinates): the rounding error is stated against the FP64 reference
+    s, ks = CASES[case]()
+    rng = np.random.default_rng(21)
+    w = rng.uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 22)
+    Ps, Pa = order
+    _say(f"[gpu] ifgf fp32 {case} n={s.n} Ps={Ps} Pa={Pa}")
+    g = _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa, precision=1)[0]
+    o2 = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params(Ps=Ps, Pa=Pa)).apply(phi[0])
+    errs = [_rel(g[q, :8], o2[q, :8]) for q in range(2)] + [_rel(g[q, 8:], o2[q, 8:]) for q in range(2)]
+    _say(f"    fp32 vs reference IFGF: S {errs[:2]}, D {errs[2:]}")
+    assert max(errs[:2]) < 2e-5
+    assert max(errs[2:]) < 1e-4
