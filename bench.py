@@ -133,9 +133,13 @@ def main():
     d = kern[dom]
     if d["flop"] > 0:
         achieved = d["flop"] / (d["ms"] * 1e-3)
-        peak = PEAK["fp64_valu"] if args.precision == "fp64" else PEAK["fp32_valu_nopk"]
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+        mfma = dom in ("propagate",)          # contraction on the matrix cores
+        if mfma:
+            peak = PEAK["fp64_valu"] if args.precision == "fp64" else PEAK["fp32_mfma"]
+        else:
+            peak = PEAK["fp64_valu"] if args.precision == "fp64" else PEAK["fp32_valu_nopk"]
+        roof = {"bound": "mfma" if mfma else "alu", "kernel": dom, "achieved": achieved / 1e12,
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
     else:
         achieved = d["bytes"] / (d["ms"] * 1e-3)
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": 8000.0,

@@ -132,6 +132,12 @@ void make_interp(InterpC& ic, int Ps, int Pa) {
   std::memset(ic.wa, 0, sizeof(ic.wa));
   fill(Ps, ic.xs, ic.ws);
   fill(Pa, ic.xa, ic.wa);
+  for (int k = 0; k < 8; ++k) {
+    ic.xsf[k] = (float)ic.xs[k];
+    ic.xaf[k] = (float)ic.xa[k];
+    ic.wsf[k] = (float)ic.ws[k];
+    ic.waf[k] = (float)ic.wa[k];
+  }
 }
 
 template <class T>

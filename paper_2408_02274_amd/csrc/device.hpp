@@ -17,6 +17,7 @@ constexpr int kOut = 2 * (kNS + kND);  // complex outputs per point
 struct InterpC {
   int Ps, Pa, npts;
   double xs[8], xa[8], ws[8], wa[8];
+  float xsf[8], xaf[8], wsf[8], waf[8];   // the same in FP32
 };
 
 struct DevLevel {

@@ -21,7 +21,7 @@ constexpr int kDotBlocks = 240;
 constexpr int kBS = 256;
 
 // part[j * kDotBlocks + b] = sum over block b's strided range of conj(V_j) w
-__global__ void k_dots(const double2* __restrict__ V, int64_t ld, const double2* __restrict__ w,
+__global__ void __launch_bounds__(256) k_dots(const double2* __restrict__ V, int64_t ld, const double2* __restrict__ w,
                        int64_t m, double2* __restrict__ part) {
   __shared__ double sre[kBS], sim[kBS];
   const int j = blockIdx.y;
@@ -58,7 +58,7 @@ __global__ void k_dots_final(const double2* __restrict__ part, int nb, int nj, d
 }
 
 // w -= sum_j V_j h_j
-__global__ void k_orth_update(const double2* __restrict__ V, int64_t ld, const double2* __restrict__ h,
+__global__ void __launch_bounds__(256) k_orth_update(const double2* __restrict__ V, int64_t ld, const double2* __restrict__ h,
                               int nj, double2* __restrict__ w, int64_t m) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
@@ -72,7 +72,7 @@ __global__ void k_orth_update(const double2* __restrict__ V, int64_t ld, const d
 }
 
 // out = a * x + y (complex a; y may be null)
-__global__ void k_axpy(double2 a, const double2* __restrict__ x, const double2* __restrict__ y,
+__global__ void __launch_bounds__(256) k_axpy(double2 a, const double2* __restrict__ x, const double2* __restrict__ y,
                        double2* __restrict__ out, int64_t m) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
@@ -86,7 +86,7 @@ __global__ void k_axpy(double2 a, const double2* __restrict__ x, const double2* 
 }
 
 // x += sum_j V_j c_j
-__global__ void k_combine(const double2* __restrict__ V, int64_t ld, const double2* __restrict__ c,
+__global__ void __launch_bounds__(256) k_combine(const double2* __restrict__ V, int64_t ld, const double2* __restrict__ c,
                           int nj, double2* __restrict__ x, int64_t m) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
@@ -99,7 +99,7 @@ __global__ void k_combine(const double2* __restrict__ V, int64_t ld, const doubl
   x[i] = make_double2(re, im);
 }
 
-__global__ void k_fill(double2* __restrict__ x, int64_t m) {
+__global__ void __launch_bounds__(256) k_fill(double2* __restrict__ x, int64_t m) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) x[i] = make_double2(0.0, 0.0);
 }

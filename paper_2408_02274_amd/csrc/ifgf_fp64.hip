@@ -121,7 +121,7 @@ __global__ void k_gather_weighted(const double2* __restrict__ dens, const int64_
   a[t] = make_double2(v.x * wi, v.y * wi);
 }
 
-__global__ void k_near(const int32_t* __restrict__ leaf_of_point, const int32_t* __restrict__ nbr_off,
+__global__ void __launch_bounds__(128) k_near(const int32_t* __restrict__ leaf_of_point, const int32_t* __restrict__ nbr_off,
                        const int32_t* __restrict__ nbr, const int32_t* __restrict__ start,
                        const int32_t* __restrict__ end, const double* __restrict__ xs,
                        const double* __restrict__ nrm, const double2* __restrict__ a, int64_t n,
@@ -166,7 +166,7 @@ __global__ void k_near(const int32_t* __restrict__ leaf_of_point, const int32_t*
   }
 }
 
-__global__ void k_leaf(DevLevel L, InterpC ic, const double* __restrict__ xs,
+__global__ void __launch_bounds__(128) k_leaf(DevLevel L, InterpC ic, const double* __restrict__ xs,
                        const double2* __restrict__ a, double k0, double k1,
                        double2* __restrict__ vals) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,7 +202,7 @@ __global__ void k_leaf(DevLevel L, InterpC ic, const double* __restrict__ xs,
     for (int m = 0; m < kNS; ++m) o[qq * kNS + m] = acc[qq][m];
 }
 
-__global__ void k_targets(DevLevel L, InterpC ic, const double* __restrict__ xs,
+__global__ void __launch_bounds__(64) k_targets(DevLevel L, InterpC ic, const double* __restrict__ xs,
                           const double* __restrict__ nrm, int64_t n, double k0, double k1,
                           const double2* __restrict__ vals, double2* __restrict__ out_s) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -291,7 +291,7 @@ __global__ void k_targets(DevLevel L, InterpC ic, const double* __restrict__ xs,
   }
 }
 
-__global__ void k_propagate(DevLevel C, DevLevel P, InterpC ic, double k0, double k1,
+__global__ void __launch_bounds__(64) k_propagate(DevLevel C, DevLevel P, InterpC ic, double k0, double k1,
                             const double2* __restrict__ vals_c, double2* __restrict__ vals_p) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.nslots * ic.npts) return;

@@ -66,9 +66,24 @@ template <class T> __device__ __forceinline__ T tsqrt(T x);
 template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 template <> __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
 
+// Chebyshev nodes and Lagrange denominators in the working precision
+template <class T> struct Nodes;
+template <> struct Nodes<float> {
+  __device__ static const float* xs(const InterpC& c) { return c.xsf; }
+  __device__ static const float* xa(const InterpC& c) { return c.xaf; }
+  __device__ static const float* ws(const InterpC& c) { return c.wsf; }
+  __device__ static const float* wa(const InterpC& c) { return c.waf; }
+};
+template <> struct Nodes<double> {
+  __device__ static const double* xs(const InterpC& c) { return c.xs; }
+  __device__ static const double* xa(const InterpC& c) { return c.xa; }
+  __device__ static const double* ws(const InterpC& c) { return c.ws; }
+  __device__ static const double* wa(const InterpC& c) { return c.wa; }
+};
+
 // Lagrange basis on P Chebyshev nodes x with inverse denominators w
-template <int P, class T>
-__device__ __forceinline__ void lag(const double* x, const double* w, T u, T* L) {
+template <int P, class T, class X>
+__device__ __forceinline__ void lag(const X* x, const X* w, T u, T* L) {
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     T p = (T)w[j];
@@ -78,8 +93,8 @@ __device__ __forceinline__ void lag(const double* x, const double* w, T u, T* L)
     L[j] = p;
   }
 }
-template <int P, class T>
-__device__ __forceinline__ void lag_d(const double* x, const double* w, T u, T* dL) {
+template <int P, class T, class X>
+__device__ __forceinline__ void lag_d(const X* x, const X* w, T u, T* dL) {
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     T acc = 0;
@@ -223,14 +238,24 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   constexpr int NPTS = NAB * 5;
   __shared__ T acc[NPTS][33];
   __shared__ T fac[4][16][4];   // per wave: per tile row, factor (re, im) for both kernels
+  __shared__ T geo[NPTS][4];    // parent interpolation points about the parent centre, and r_p
   const int64_t q = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < NPTS * 33; i += 256) (&acc[0][0])[i] = (T)0;
-  __syncthreads();
   const int32_t pb = P.slot_box[q];
   const int pcone = P.slot_cone[q];
   const double* cp = P.centers + 3 * pb;
+  if (tid < NPTS) {
+    T s, ux, uy, uz;
+    cone_node<PS, T>(P.ns, P.na, pcone, tid, ic, &s, &ux, &uy, &uz);
+    const T rp = (T)P.h / s;
+    geo[tid][0] = rp * ux;
+    geo[tid][1] = rp * uy;
+    geo[tid][2] = rp * uz;
+    geo[tid][3] = rp;
+  }
+  __syncthreads();
   const int64_t g0 = G.off[q], g1 = G.off[q + 1];
   const int r16 = lane & 15, gl = lane >> 4;
   const T kk[2] = {(T)k0, (T)k1};
@@ -248,26 +273,23 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       const bool valid = t0 + r16 < cnt;
       const int p = valid ? (int)G.pts[pstart + t0 + r16] : 0;
       // geometry of parent point p in parent-centred coordinates, then about the child
-      T s, ux, uy, uz;
-      cone_node<PS, T>(P.ns, P.na, pcone, p, ic, &s, &ux, &uy, &uz);
-      const T rp = (T)P.h / s;
-      const T Yx = rp * ux, Yy = rp * uy, Yz = rp * uz;
+      const T Yx = geo[p][0], Yy = geo[p][1], Yz = geo[p][2], rp = geo[p][3];
       T rc, us, ut, up, th, ph;
       local3<T>(Yx - dx, Yy - dy, Yz - dz, (T)C.h, C.ns, C.na, ccone, &rc, &us, &ut, &up, &th, &ph);
       T Ls[PS], Lt[5], Lp[5];
-      lag<PS, T>(ic.xs, ic.ws, us, Ls);
-      lag<5, T>(ic.xa, ic.wa, ut, Lt);
-      lag<5, T>(ic.xa, ic.wa, up, Lp);
-      if (gl == 0) {
-        // re-centring factor G(X, x_child) / G(X, x_parent) = (rp / rc) exp(i k (rc - rp))
+      lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, Ls);
+      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
+      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
+      {
+        // re-centring factor G(X, x_child) / G(X, x_parent) = (rp / rc) exp(i k (rc - rp));
+        // lane group gl evaluates kernel gl & 1, groups 0 and 1 store it
         const T diff = (d2 - (T)2 * (Yx * dx + Yy * dy + Yz * dz)) / (rc + rp);
         const T ratio = rp / rc;
-#pragma unroll
-        for (int qq = 0; qq < 2; ++qq) {
-          T sn, cs;
-          tsincos<T>(kk[qq] * diff, &sn, &cs);
-          fac[wave][r16][2 * qq] = ratio * cs;
-          fac[wave][r16][2 * qq + 1] = ratio * sn;
+        T sn, cs;
+        tsincos<T>(kk[gl & 1] * diff, &sn, &cs);
+        if (gl < 2) {
+          fac[wave][r16][2 * gl] = ratio * cs;
+          fac[wave][r16][2 * gl + 1] = ratio * sn;
         }
       }
       const T lpg = gl == 0 ? Lp[0] : gl == 1 ? Lp[1] : gl == 2 ? Lp[2] : Lp[3];
@@ -354,12 +376,12 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
     T r, us, ut, up, th, ph;
     local3<T>(zx, zy, zz, (T)L.h, L.ns, L.na, cone, &r, &us, &ut, &up, &th, &ph);
     T Ls[PS], Lt[5], Lp[5], dLs[PS], dLt[5], dLp[5];
-    lag<PS, T>(ic.xs, ic.ws, us, Ls);
-    lag<5, T>(ic.xa, ic.wa, ut, Lt);
-    lag<5, T>(ic.xa, ic.wa, up, Lp);
-    lag_d<PS, T>(ic.xs, ic.ws, us, dLs);
-    lag_d<5, T>(ic.xa, ic.wa, ut, dLt);
-    lag_d<5, T>(ic.xa, ic.wa, up, dLp);
+    lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, Ls);
+    lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
+    lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
+    lag_d<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, dLs);
+    lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, dLt);
+    lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, dLp);
     const T rinv = (T)1 / r;
     const T n_r = (nx * zx + ny * zy + nz * zz) * rinv;
     T st, ct, sp, cp;

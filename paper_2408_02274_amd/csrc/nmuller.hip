@@ -56,7 +56,7 @@ __device__ __forceinline__ double2 rdot(const double* t, const c3& a) {
 }
 
 // a1: unknowns (m.t1, m.t2, j.t1, j.t2) -> eight densities (m, j, div m, div j)
-__global__ void k_pre(GeoDev g, const double2* __restrict__ y, double2* __restrict__ phi) {
+__global__ void __launch_bounds__(256) k_pre(GeoDev g, const double2* __restrict__ y, double2* __restrict__ phi) {
   __shared__ double2 s[4][kMaxNq];   // J a^u (m), J a^v (m), J a^u (j), J a^v (j)
   const int nq = g.nc * g.nc;
   const int p = blockIdx.x;
@@ -95,7 +95,7 @@ __global__ void k_pre(GeoDev g, const double2* __restrict__ y, double2* __restri
 }
 
 // a7: out += C phi for the singular patches of every target (one wavefront per target)
-__global__ void k_correct(const int64_t* __restrict__ row_off, const int32_t* __restrict__ pair_patch,
+__global__ void __launch_bounds__(256) k_correct(const int64_t* __restrict__ row_off, const int32_t* __restrict__ pair_patch,
                           const double2* __restrict__ vals, int nq, int64_t n,
                           const double2* __restrict__ phi, double2* __restrict__ out, int nrhs) {
   const int lane = threadIdx.x & 63;
@@ -104,12 +104,14 @@ __global__ void k_correct(const int64_t* __restrict__ row_off, const int32_t* __
   if (l >= n || r >= nrhs) return;
   const double2* ph = phi + (int64_t)r * 8 * n;
   double2 acc[28];
+#pragma unroll
   for (int k = 0; k < 28; ++k) acc[k] = make_double2(0.0, 0.0);
   for (int64_t e = row_off[l]; e < row_off[l + 1]; ++e) {
     const int64_t base = (int64_t)pair_patch[e] * nq;
     const double2* C = vals + e * 4 * nq;
     for (int q = lane; q < nq; q += 64) {
       double2 w0 = C[q], w1 = C[nq + q], w2 = C[2 * nq + q], w3 = C[3 * nq + q];
+#pragma unroll
       for (int c = 0; c < 8; ++c) {
         double2 f = ph[c * n + base + q];
         acc[c] = cadd(acc[c], cmulc(w0, f));            // S, k_int
@@ -121,6 +123,7 @@ __global__ void k_correct(const int64_t* __restrict__ row_off, const int32_t* __
       }
     }
   }
+#pragma unroll
   for (int k = 0; k < 28; ++k) {
     double re = acc[k].x, im = acc[k].y;
     for (int off = 32; off > 0; off >>= 1) {
@@ -132,6 +135,7 @@ __global__ void k_correct(const int64_t* __restrict__ row_off, const int32_t* __
   if (lane < 28) {
     double2* o = out + (int64_t)r * 28 * n + (int64_t)lane * n + l;
     double2 v = acc[0];
+#pragma unroll
     for (int k = 1; k < 28; ++k)
       if (k == lane) v = acc[k];
     *o = cadd(*o, v);
@@ -143,7 +147,7 @@ struct Mat {
 };
 
 // a8: K, R, T from S and D, Delta-combinations and identity terms, projection on t1, t2
-__global__ void k_post(GeoDev g, Mat mt, const double2* __restrict__ y,
+__global__ void __launch_bounds__(256) k_post(GeoDev g, Mat mt, const double2* __restrict__ y,
                        const double2* __restrict__ SD, double2* __restrict__ Ay) {
   __shared__ double2 s[16][kMaxNq];   // S_q[phi_c], q = 0,1, c = 0..7
   const int nq = g.nc * g.nc;
