@@ -78,6 +78,10 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--ifgf-only", action="store_true",
+                    help="time the raw IFGF sums only (no N-Mueller plan: seconds to set up)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run one device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding across GPUs "
@@ -94,17 +98,35 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.copy_calib > 0:
+        nb = args.copy_calib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes read, {nb} bytes written")
+        del src, dst
+
     surf = synth.cube_sphere(args.npf, 10, args.radius)
     eps_e, eps_i = 1.0, 2.25
+    prec = B.IFGF_FP64 if args.precision == "fp64" else B.IFGF_FP32
     t0 = time.perf_counter()
-    op = NMullerOperator(surf, eps_e, eps_i, tol=args.tol,
-                         precision=B.IFGF_FP64 if args.precision == "fp64" else B.IFGF_FP32)
+    if args.ifgf_only:
+        from paper_2408_02274_amd import IFGFPlan
+        ks = (2 * math.pi * math.sqrt(eps_i), 2 * math.pi * math.sqrt(eps_e))
+        w = np.full(surf.n, 4.0 * math.pi * args.radius ** 2 / surf.n)
+        op = IFGFPlan(surf.x, surf.normal, w, ks[0], ks[1], args.tol, precision=prec)
+        ih = op.handle
+        y = torch.from_numpy(synth.complex_normal((1, 8, surf.n), 2)).to("cuda")
+        out = torch.empty((1, 2, 14, surf.n), dtype=torch.complex128, device="cuda")
+        args.no_gmres = True
+    else:
+        op = NMullerOperator(surf, eps_e, eps_i, tol=args.tol, precision=prec)
+        ih = op.ifgf_handle()
+        y = torch.from_numpy(synth.complex_normal((1, 4, surf.n), 2)).to("cuda")
+        out = torch.empty_like(y)
     plan_s = time.perf_counter() - t0
     log(f"plan built in {plan_s:.1f} s (n = {surf.n})")
-    ih = op.ifgf_handle()
-    st0 = B.ifgf_stats(ih)
-    y = torch.from_numpy(synth.complex_normal((1, 4, surf.n), 2)).to("cuda")
-    out = torch.empty_like(y)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         op.apply(y, out)
@@ -170,7 +192,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"N-Mueller forward map, dielectric sphere radius {args.radius} "
+        "config": {"workload": ("IFGF raw sums only: " if args.ifgf_only else "") +
+                               f"N-Mueller forward map, dielectric sphere radius {args.radius} "
                                f"(eps_r 2.25 in vacuum, k_int = 3 pi, k_ext = 2 pi), 6x{args.npf}x{args.npf} "
                                f"patches x 10x10 Chebyshev nodes ({surf.n} points, {4 * surf.n} unknowns), "
                                f"IFGF tol {args.tol}, 1 RHS",
@@ -183,7 +206,7 @@ def main():
     }
     if not args.no_cpu:
         ks = (2 * math.pi * math.sqrt(eps_i), 2 * math.pi * math.sqrt(eps_e))
-        w = op.geometry(1)
+        w = np.full(surf.n, 4.0 * math.pi * args.radius ** 2 / surf.n) if args.ifgf_only else op.geometry(1)
         res["cpu_baseline"] = cpu_baseline(surf, ks, w, args.cpu_rows)
     print(json.dumps(res), flush=True)
     op.close()

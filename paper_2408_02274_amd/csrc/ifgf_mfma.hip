@@ -151,6 +151,16 @@ __device__ __forceinline__ void local3(T zx, T zy, T zz, T h, int ns, int na, in
   *up = (*ph - ((T)ip + (T)0.5) * da) / ((T)0.5 * da);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8),
+// each XCD with its own L2.  Map blocks so that every XCD works on one
+// contiguous range of work items: neighbouring cones (which share child cones
+// and cousin data) then meet in the same L2.  A bijection of [0, nblocks).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  const int64_t x = bid & 7, i = bid >> 3;
+  const int64_t per = nblocks >> 3, rem = nblocks & 7;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 __device__ __forceinline__ int point_of_row(int row, int nab) {
   if (row < 4 * nab) return 5 * (row >> 2) + (row & 3);
   int m = row - 4 * nab;
@@ -181,7 +191,7 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
                          double k0, double k1, T* __restrict__ V) {
   constexpr int NAB = PS * 5;
   constexpr int K = 4 * (NAB + (NAB + 3) / 4);
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= L.nslots * K) return;
   int64_t q = t / K;
   int row = (int)(t % K);
@@ -227,7 +237,11 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
 }
 
 // ---------------------------------------------------------------------------
-// propagation: one workgroup per parent cone slot, 4 wavefronts
+// propagation: one workgroup per parent cone slot, 4 wavefronts.  The tiles
+// (16 parent points of one child cone) are dealt round-robin to the
+// wavefronts.  A wavefront takes its tiles four at a time: one lane per point
+// evaluates the child-cone coordinates, Lagrange factors and re-centring
+// factor of its point into wave-private LDS, then the four MFMA tiles run.
 template <int PS, class T>
 __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, InterpC ic, PropGroups G,
                                                    double k0, double k1, const T* __restrict__ Vc,
@@ -236,12 +250,14 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   constexpr int KS = NAB + (NAB + 3) / 4;
   constexpr int K = 4 * KS;
   constexpr int NPTS = NAB * 5;
+  constexpr int GW = 20;                // Ls [0, PS), Lt [6, 11), Lp [11, 16), factor [16, 20)
   __shared__ T acc[NPTS][33];
-  __shared__ T fac[4][16][4];   // per wave: per tile row, factor (re, im) for both kernels
-  __shared__ T geo[NPTS][4];    // parent interpolation points about the parent centre, and r_p
-  const int64_t q = blockIdx.x;
+  __shared__ T gbuf[4][64][GW];         // per wavefront: 4 tiles x 16 rows
+  __shared__ T geo[NPTS][4];            // parent points about the parent centre, and r_p
+  const int64_t q = xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, gl = lane >> 4;
   for (int i = tid; i < NPTS * 33; i += 256) (&acc[0][0])[i] = (T)0;
   const int32_t pb = P.slot_box[q];
   const int pcone = P.slot_cone[q];
@@ -256,82 +272,140 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
     geo[tid][3] = rp;
   }
   __syncthreads();
-  const int64_t g0 = G.off[q], g1 = G.off[q + 1];
-  const int r16 = lane & 15, gl = lane >> 4;
   const T kk[2] = {(T)k0, (T)k1};
-  for (int64_t g = g0 + wave; g < g1; g += 4) {
-    const int32_t slot = G.slot[g];
-    const int32_t cb = G.cbox[g];
-    const int64_t pstart = G.start[g];
-    const int cnt = G.count[g];
-    const int ccone = C.slot_cone[slot];
-    const double* cc = C.centers + 3 * cb;
-    const T dx = (T)(cc[0] - cp[0]), dy = (T)(cc[1] - cp[1]), dz = (T)(cc[2] - cp[2]);
-    const T d2 = dx * dx + dy * dy + dz * dz;
-    const T* Vs = Vc + (int64_t)slot * K * 32;
-    for (int t0 = 0; t0 < cnt; t0 += 16) {
-      const bool valid = t0 + r16 < cnt;
-      const int p = valid ? (int)G.pts[pstart + t0 + r16] : 0;
-      // geometry of parent point p in parent-centred coordinates, then about the child
-      const T Yx = geo[p][0], Yy = geo[p][1], Yz = geo[p][2], rp = geo[p][3];
-      T rc, us, ut, up, th, ph;
-      local3<T>(Yx - dx, Yy - dy, Yz - dz, (T)C.h, C.ns, C.na, ccone, &rc, &us, &ut, &up, &th, &ph);
-      T Ls[PS], Lt[5], Lp[5];
-      lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, Ls);
-      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
-      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
-      {
-        // re-centring factor G(X, x_child) / G(X, x_parent) = (rp / rc) exp(i k (rc - rp));
-        // lane group gl evaluates kernel gl & 1, groups 0 and 1 store it
-        const T diff = (d2 - (T)2 * (Yx * dx + Yy * dy + Yz * dz)) / (rc + rp);
-        const T ratio = rp / rc;
-        T sn, cs;
-        tsincos<T>(kk[gl & 1] * diff, &sn, &cs);
-        if (gl < 2) {
-          fac[wave][r16][2 * gl] = ratio * cs;
-          fac[wave][r16][2 * gl + 1] = ratio * sn;
+  const T two_ds = (T)(2.0 * C.ns / kEtaD), two_da = (T)(2.0 * C.na / kPiD);
+  const int64_t g0 = G.off[q], g1 = G.off[q + 1];
+  T(*gb)[GW] = gbuf[wave];
+  // walk the tile sequence; this wavefront owns tiles with index % 4 == wave
+  int64_t bg[4];
+  int bt[4];
+  int nb = 0, tcount = 0;
+  int64_t g = g0;
+  int t0 = 0;
+  while (true) {
+    // collect up to 4 owned tiles
+    nb = 0;
+    while (g < g1 && nb < 4) {
+      const int cnt = G.count[g];
+      if ((tcount & 3) == wave) {
+        bg[nb] = g;
+        bt[nb] = t0;
+        ++nb;
+      }
+      ++tcount;
+      t0 += 16;
+      if (t0 >= cnt) {
+        t0 = 0;
+        ++g;
+      }
+    }
+    if (nb == 0) break;
+    // geometry: lane -> (tile lane / 16, row lane % 16)
+    {
+      const int b = gl;
+      if (b < nb) {
+        const int64_t gg = bg[b];
+        const int cnt = G.count[gg];
+        const int tt = bt[b];
+        const bool valid = tt + r16 < cnt;
+        const int p = valid ? (int)G.pts[G.start[gg] + tt + r16] : 0;
+        const int32_t slot = G.slot[gg];
+        const int cone = C.slot_cone[slot];
+        const double* cc = C.centers + 3 * G.cbox[gg];
+        const T dx = (T)(cc[0] - cp[0]), dy = (T)(cc[1] - cp[1]), dz = (T)(cc[2] - cp[2]);
+        const T Yx = geo[p][0], Yy = geo[p][1], Yz = geo[p][2], rp = geo[p][3];
+        const T zx = Yx - dx, zy = Yy - dy, zz = Yz - dz;
+        const T rc = tsqrt<T>(zx * zx + zy * zy + zz * zz);
+        const T rci = (T)1 / rc;
+        T ct = zz * rci;
+        ct = ct > (T)1 ? (T)1 : (ct < (T)-1 ? (T)-1 : ct);
+        const T th = tacos<T>(ct);
+        T ph = tatan2<T>(zy, zx);
+        if (ph < (T)0) ph += (T)(2.0 * kPiD);
+        const int ip = cone % (2 * C.na);
+        const int it = (cone / (2 * C.na)) % C.na;
+        const int is = cone / (2 * C.na * C.na);
+        const T us = (T)C.h * rci * two_ds - (T)(2 * is + 1);
+        const T ut = th * two_da - (T)(2 * it + 1);
+        const T up = ph * two_da - (T)(2 * ip + 1);
+        T L[PS], Lt[5], Lp[5];
+        lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, L);
+        lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
+        lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
+        const T vm = valid ? (T)1 : (T)0;
+#pragma unroll
+        for (int z = 0; z < PS; ++z) gb[lane][z] = L[z] * vm;
+#pragma unroll
+        for (int z = 0; z < 5; ++z) {
+          gb[lane][6 + z] = Lt[z];
+          gb[lane][11 + z] = Lp[z];
+        }
+        // re-centring factor G(X, x_child) / G(X, x_parent) = (rp / rc) exp(i k (rc - rp))
+        const T diff = (dx * dx + dy * dy + dz * dz - (T)2 * (Yx * dx + Yy * dy + Yz * dz)) / (rc + rp);
+        const T ratio = rp * rci;
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+          T sn, cs;
+          tsincos<T>(kk[qq] * diff, &sn, &cs);
+          gb[lane][16 + 2 * qq] = ratio * cs;
+          gb[lane][17 + 2 * qq] = ratio * sn;
         }
       }
-      const T lpg = gl == 0 ? Lp[0] : gl == 1 ? Lp[1] : gl == 2 ? Lp[2] : Lp[3];
-      const T vmask = valid ? (T)1 : (T)0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int b = 0; b < nb; ++b) {
+      const int64_t gg = bg[b];
+      const int cnt = G.count[gg];
+      const int tt = bt[b];
+      const int64_t pstart = G.start[gg] + tt;
+      const T* Vs = Vc + (int64_t)G.slot[gg] * K * 32 + gl * 32;
+      const T* me = gb[16 * b + r16];
+      T Ls[PS], Lt[5];
+#pragma unroll
+      for (int z = 0; z < PS; ++z) Ls[z] = me[z];
+#pragma unroll
+      for (int z = 0; z < 5; ++z) Lt[z] = me[6 + z];
+      const T lpg = me[11 + gl];
+      const T lp4 = me[15];
+      T st[NAB];
+#pragma unroll
+      for (int ab = 0; ab < NAB; ++ab) st[ab] = Ls[ab / 5] * Lt[ab % 5];
       typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
         T av;
         if (j < NAB) {
-          av = Ls[j / 5] * Lt[j % 5] * lpg;
+          av = st[j] * lpg;
         } else {
-          const int m = 4 * (j - NAB) + gl;
-          const int ma = m / 5, mb = m % 5;
-          T la = (T)0, lb = (T)0;
-#pragma unroll
-          for (int z = 0; z < PS; ++z) la = (ma == z) ? Ls[z] : la;
-#pragma unroll
-          for (int z = 0; z < 5; ++z) lb = (mb == z) ? Lt[z] : lb;
-          av = m < NAB ? la * lb * Lp[4] : (T)0;
+          // slot 4 j + gl holds phi-node 4 of (a, b) pair m = 4 (j - NAB) + gl
+          const int m0 = 4 * (j - NAB);
+          T sel = (m0 < NAB) ? st[m0 < NAB ? m0 : 0] : (T)0;
+          sel = (gl == 1) ? ((m0 + 1 < NAB) ? st[m0 + 1 < NAB ? m0 + 1 : 0] : (T)0) : sel;
+          sel = (gl == 2) ? ((m0 + 2 < NAB) ? st[m0 + 2 < NAB ? m0 + 2 : 0] : (T)0) : sel;
+          sel = (gl == 3) ? ((m0 + 3 < NAB) ? st[m0 + 3 < NAB ? m0 + 3 : 0] : (T)0) : sel;
+          av = sel * lp4;
         }
-        av *= vmask;
-        const T* vrow = Vs + (int64_t)(4 * j + gl) * 32;
+        const T* vrow = Vs + (int64_t)(4 * j) * 32;
         c0 = MF<T>::mma(av, vrow[r16], c0);
         c1 = MF<T>::mma(av, vrow[16 + r16], c1);
       }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       // lane holds rows MF::row(lane, e), complex column r16 (kernel r16 / 8)
       const int qq = r16 >> 3;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int orow = MF<T>::row(lane, e);
-        if (t0 + orow < cnt) {
-          const int po = (int)G.pts[pstart + t0 + orow];
-          const T fr = fac[wave][orow][2 * qq], fi = fac[wave][orow][2 * qq + 1];
+        if (tt + orow < cnt) {
+          const int po = (int)G.pts[pstart + orow];
+          const T fr = gb[16 * b + orow][16 + 2 * qq], fi = gb[16 * b + orow][17 + 2 * qq];
           const T vr = c0[e], vi = c1[e];
           atomicAdd(&acc[po][r16], fr * vr - fi * vi);
           atomicAdd(&acc[po][16 + r16], fr * vi + fi * vr);
         }
       }
-      __builtin_amdgcn_wave_barrier();
     }
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   T* out = Vp + q * (int64_t)K * 32;
@@ -351,7 +425,7 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
   constexpr int NAB = PS * 5;
   constexpr int KS = NAB + (NAB + 3) / 4;
   constexpr int K = 4 * KS;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t e0 = L.tp_off[i], e1 = L.tp_off[i + 1];
   if (e0 == e1) return;
