@@ -274,32 +274,22 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   __syncthreads();
   const T kk[2] = {(T)k0, (T)k1};
   const T two_ds = (T)(2.0 * C.ns / kEtaD), two_da = (T)(2.0 * C.na / kPiD);
-  const int64_t g0 = G.off[q], g1 = G.off[q + 1];
   T(*gb)[GW] = gbuf[wave];
-  // walk the tile sequence; this wavefront owns tiles with index % 4 == wave
+  const int64_t t_beg = G.toff[q], t_end = G.toff[q + 1];
   int64_t bg[4];
   int bt[4];
-  int nb = 0, tcount = 0;
-  int64_t g = g0;
-  int t0 = 0;
-  while (true) {
-    // collect up to 4 owned tiles
-    nb = 0;
-    while (g < g1 && nb < 4) {
-      const int cnt = G.count[g];
-      if ((tcount & 3) == wave) {
-        bg[nb] = g;
-        bt[nb] = t0;
-        ++nb;
-      }
-      ++tcount;
-      t0 += 16;
-      if (t0 >= cnt) {
-        t0 = 0;
-        ++g;
+  // this wavefront owns tiles t_beg + wave + 4 i, taken four at a time
+  for (int64_t tb = t_beg + wave; tb < t_end; tb += 16) {
+    int nb = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t tl = tb + 4 * b;
+      if (tl < t_end) {
+        bg[b] = G.tg[tl];
+        bt[b] = G.tt0[tl];
+        nb = b + 1;
       }
     }
-    if (nb == 0) break;
     // geometry: lane -> (tile lane / 16, row lane % 16)
     {
       const int b = gl;

@@ -20,6 +20,9 @@ struct PropGroups {
   const int64_t* start = nullptr;
   const int32_t* count = nullptr;
   const uint8_t* pts = nullptr;
+  const int64_t* toff = nullptr;   // tiles of parent slot q: [toff[q], toff[q+1])
+  const int32_t* tg = nullptr;     // group of each tile
+  const uint8_t* tt0 = nullptr;    // first point (within the group) of each tile
 };
 
 bool mfma_path_supported(int Ps, int Pa);

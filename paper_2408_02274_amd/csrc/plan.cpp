@@ -142,6 +142,23 @@ void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts) {
       st += gn[q][i];
     }
   }
+  Pl.pt_off.assign(Q + 1, 0);
+  for (int64_t q = 0; q < Q; ++q) {
+    int64_t nt = 0;
+    for (int64_t g = Pl.pg_off[q]; g < Pl.pg_off[q + 1]; ++g) nt += (Pl.pg_count[g] + 15) / 16;
+    Pl.pt_off[q + 1] = Pl.pt_off[q] + nt;
+  }
+  Pl.pt_g.resize(Pl.pt_off[Q]);
+  Pl.pt_t0.resize(Pl.pt_off[Q]);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t q = 0; q < Q; ++q) {
+    int64_t t = Pl.pt_off[q];
+    for (int64_t g = Pl.pg_off[q]; g < Pl.pg_off[q + 1]; ++g)
+      for (int t0 = 0; t0 < Pl.pg_count[g]; t0 += 16, ++t) {
+        Pl.pt_g[t] = (int32_t)g;
+        Pl.pt_t0[t] = (uint8_t)t0;
+      }
+  }
   (void)L;
 }
 

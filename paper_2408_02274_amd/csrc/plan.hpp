@@ -45,6 +45,11 @@ struct HostLevel {
   std::vector<int64_t> pg_off, pg_start;
   std::vector<int32_t> pg_slot, pg_cbox, pg_count;
   std::vector<uint8_t> pg_pts;
+  // 16-point tiles of those groups: for parent slot q the tiles
+  // [pt_off[q], pt_off[q+1]); tile t covers points pt_t0[t] .. +16 of group pt_g[t]
+  std::vector<int64_t> pt_off;
+  std::vector<int32_t> pt_g;
+  std::vector<uint8_t> pt_t0;
 };
 
 struct HostPlan {
