@@ -118,6 +118,13 @@ int ifgf_plan_table(ifgf_plan_t plan, int which, int64_t* buf, int64_t cap,
  * synchronises on the recorded events.                                     */
 int ifgf_stats(ifgf_plan_t plan, char* json, size_t cap);
 
+/* Switch the working precision of a built plan (IFGF_FP64 or IFGF_FP32)
+ * for the following apply calls; `previous` (may be NULL) receives the one
+ * in force before.  The FP64 and FP32 forms share the plan tables; FP32 is
+ * available when Pa = 5 and 3 <= Ps <= 6 (else IFGF_EINVAL).  Used by the
+ * mixed-precision solve: Arnoldi on the FP32 form, residuals on the FP64.   */
+int ifgf_set_precision(ifgf_plan_t plan, int precision, int* previous);
+
 /* Switch per-kernel timing on (1) or off (0); either resets the totals.    */
 int ifgf_set_timing(ifgf_plan_t plan, int on);
 

@@ -65,6 +65,8 @@ def lib():
         L.ifgf_stats.argtypes = [vp, C.c_char_p, C.c_size_t]
         L.ifgf_set_timing.argtypes = [vp, ci]
         L.ifgf_set_timing.restype = ci
+        L.ifgf_set_precision.argtypes = [vp, ci, C.POINTER(ci)]
+        L.ifgf_set_precision.restype = ci
         L.ifgf_destroy.argtypes = [vp]
         L.ifgf_destroy.restype = None
         L.ifgf_last_error.restype = C.c_char_p
@@ -174,6 +176,13 @@ def ifgf_stats(plan):
 
 def ifgf_set_timing(plan, on):
     _check(lib().ifgf_set_timing(plan, int(bool(on))), "ifgf_set_timing")
+
+
+def ifgf_set_precision(plan, precision):
+    """Switch a built plan to IFGF_FP64 or IFGF_FP32; returns the previous one."""
+    prev = C.c_int(0)
+    _check(lib().ifgf_set_precision(plan, int(precision), C.byref(prev)), "ifgf_set_precision")
+    return prev.value
 
 
 def ifgf_destroy(plan):

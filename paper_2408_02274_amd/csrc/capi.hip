@@ -334,7 +334,9 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     delete p;
     return set_error(IFGF_ENOMEM, "device workspace allocation failed");
   }
-  if (p->fp32) {
+  // A matrix-core plan can run in either precision (ifgf_set_precision), so
+  // its FP32 density copy and FP64-sized cone buffers always exist.
+  if (p->mfma) {
     p->d_af = ar.alloc(sizeof(float) * 16 * (size_t)n);
     if (!p->d_af) {
       delete p;
@@ -342,8 +344,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     }
   }
   if (p->max_slots > 0) {
-    size_t vb = p->mfma ? (p->fp32 ? sizeof(float) : sizeof(double)) * (size_t)p->max_slots *
-                              kslot_rows(opt.Ps) * 32
+    size_t vb = p->mfma ? sizeof(double) * (size_t)p->max_slots * kslot_rows(opt.Ps) * 32
                         : sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
     p->d_vals[0] = static_cast<double2*>(ar.alloc(vb));
     p->d_vals[1] = static_cast<double2*>(ar.alloc(vb));
@@ -520,6 +521,20 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
   s += "}}";
   if (s.size() + 1 > cap) return set_error(IFGF_EINVAL, "json buffer too small");
   std::memcpy(json, s.c_str(), s.size() + 1);
+  return IFGF_OK;
+}
+
+int ifgf_set_precision(ifgf_plan_t p, int precision, int* previous) {
+  clear_error();
+  if (!p) return set_error(IFGF_EINVAL, "plan is NULL");
+  if (precision != IFGF_FP64 && precision != IFGF_FP32)
+    return set_error(IFGF_EINVAL, "precision must be IFGF_FP64 or IFGF_FP32");
+  if (p->opt.host_only) return set_error(IFGF_ENOTPLANNED, "plan was built with host_only");
+  if (precision == IFGF_FP32 && !p->mfma)
+    return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 and 3 <= Ps <= 6");
+  if (previous) *previous = p->fp32 ? IFGF_FP32 : IFGF_FP64;
+  p->fp32 = precision == IFGF_FP32;
+  p->opt.precision = precision;
   return IFGF_OK;
 }
 

@@ -112,3 +112,33 @@ def test_fp32_cone_grids_close_to_reference(case, order):
     _say(f"    fp32 vs reference IFGF: S {errs[:2]}, D {errs[2:]}")
     assert max(errs[:2]) < 2e-5
     assert max(errs[2:]) < 1e-4
+
+
+def test_precision_switch_reproduces_fp64_plan():
+    """An FP32 plan switched to FP64 runs the same FP64 kernels on the same
+    tables as a plan built in FP64: equal results up to the summation order
+    of the propagation's LDS accumulation (not fixed between runs); switched
+    back, it reproduces its own FP32 output to that order as well."""
+    from paper_2408_02274_amd import IFGFPlan
+    from paper_2408_02274_amd import binding as B
+    s = synth.cube_sphere(2, 8, 1.0)
+    ks = (3 * math.pi, 2 * math.pi)
+    w = np.random.default_rng(5).uniform(0.5, 1.5, s.n)
+    d = torch.from_numpy(synth.complex_normal((1, 8, s.n), 6)).to("cuda")
+    _say("[gpu] precision switch sphere_c1")
+    p64 = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-3, Ps=5, Pa=5)
+    p32 = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-3, Ps=5, Pa=5, precision=B.IFGF_FP32)
+    a = p64.apply(d).cpu().numpy()
+    f1 = p32.apply(d).cpu().numpy()
+    assert B.ifgf_set_precision(p32.handle, B.IFGF_FP64) == B.IFGF_FP32
+    b = p32.apply(d).cpu().numpy()
+    assert B.ifgf_set_precision(p32.handle, B.IFGF_FP32) == B.IFGF_FP64
+    f2 = p32.apply(d).cpu().numpy()
+    torch.cuda.synchronize()
+    assert _rel(b, a) < 1e-13
+    assert _rel(f2, f1) < 1e-6
+    assert _rel(f1, a) < 1e-4
+    with pytest.raises(B.IFGFError):
+        B.ifgf_set_precision(p64.handle, 7)
+    p32.close()
+    p64.close()

@@ -62,3 +62,25 @@ def test_table2_row1_against_paper():
     # the paper: 27 iterations and 9.71e-5 with IFGF, 26 and 8.8e-5 without
     assert abs(info["iters"] - gold["iterations_cbie_ifgf"]) <= 0.25 * gold["iterations_cbie_ifgf"]
     assert err < 2.5 * gold["error_cbie_ifgf"]
+
+
+def test_mixed_precision_solve_meets_fp64_residual():
+    """FP32 IFGF inside the Arnoldi process, FP64 residuals deciding the
+    exit: the reported residual is the one an FP64-only operator sees."""
+    from paper_2408_02274_amd import NMullerOperator
+    from paper_2408_02274_amd import binding as B
+    s = synth.cube_sphere(2, 8, 1.0)
+    surf = surface.PatchSurface(s.P, s.nc, s.x, s.du, s.dv)
+    nm_o = nmuller.NMuller(surf, 1.0, 2.25, corrections={})
+    E, H = nm_o.incident_plane_wave([0, 0, 1.0], [1.0, 0, 0])
+    _say("[gpu] nmuller_solve mixed precision config1")
+    op32 = NMullerOperator(s, 1.0, 2.25, tol=1e-3, Ps=5, Pa=5, precision=B.IFGF_FP32)
+    op64 = NMullerOperator(s, 1.0, 2.25, tol=1e-3, Ps=5, Pa=5)
+    b = op32.rhs(torch.from_numpy(E[None]).to("cuda"), torch.from_numpy(H[None]).to("cuda"))
+    y, info = op32.solve(b, rtol=1e-4, maxit=300)
+    rel64 = float(torch.linalg.norm(b - op64.apply(y)) / torch.linalg.norm(b))
+    _say(info, rel64)
+    assert info[0]["converged"] and rel64 <= 1e-4
+    assert abs(rel64 - info[0]["true_relres"]) < 1e-9
+    op32.close()
+    op64.close()
