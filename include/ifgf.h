@@ -199,6 +199,8 @@ typedef struct {
   double true_relres;     /* ||b - A y|| / ||b|| from a final FP64 matvec      */
   double arnoldi_relres;  /* GMRES residual estimate at exit                   */
   double seconds;         /* host wall time of this right-hand side            */
+  int precond_iters;      /* iterations run with the network part of M on      */
+  int fallbacks;          /* preconditioned cycles abandoned (see below)       */
 } ifgf_solve_info;
 
 /* Solve A y = b by GMRES (Sec. III-A eq. lin_system): Arnoldi in FP64 with
@@ -212,6 +214,94 @@ typedef struct {
  * iterate is still returned.  Synchronises the stream once per iteration.  */
 int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, int use_x0, double rtol,
                   int maxit, int restart, ifgf_solve_info* info, void* stream);
+
+/* Unrestarted GMRES from y = 0 that also records iterates: after every
+ * `stride`-th iteration k it writes x_k to X[j] and its residual
+ * r_k = b - A x_k (from the Arnoldi relation, no extra matvec) to R[j],
+ * j = 0, 1, .. < cap; *nrec receives the number written.  X, R device
+ * [cap][4][n] complex FP64; rhs, y as for nmuller_solve (nrhs = 1).  Used to
+ * generate (residual, error) training pairs for the learned preconditioner
+ * (project addition).  Unlike nmuller_solve, every residual here (and
+ * info->true_relres) is taken with the operator's working precision, so a
+ * plan running its FP32 form can be driven to tolerances below its FP32
+ * error.  Returns IFGF_WNOCONV like nmuller_solve.                         */
+int nmuller_solve_trajectory(nmuller_t nm, const void* rhs, void* y, double rtol, int maxit,
+                             int stride, void* X, void* R, int cap, int* nrec,
+                             ifgf_solve_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned FGMRES preconditioner (project addition; the paper uses plain
+ * GMRES).  z = M(v) acts on each patch separately: a network with ReLU
+ * hidden layers maps the patch's 4 Nc^2 complex unknowns (real parts then
+ * imaginary parts of each of the four components, node order of the patch,
+ * divided by s = rms(v)) followed by 4 patch features (kappa_e d / 2pi,
+ * kappa_i d / 2pi, twice the largest normal deviation angle, eps_i / eps_e / 10,
+ * d = node bounding-box diagonal) to a correction c of the same 8 Nc^2 layout;
+ * z = D^-1 v + s c, D = diag((mu_e+mu_i)/2, (eps_e+eps_i)/2) the identity part
+ * of eq. n_muller.  With a preconditioner set, nmuller_solve runs flexible
+ * GMRES; a cycle whose network output is non-finite or whose residual
+ * estimate falls by less than 5% over 20 iterations is abandoned at its last
+ * good column and the solve continues with the network switched off
+ * (M = D^-1); ifgf_solve_info counts these fallbacks.
+ * ------------------------------------------------------------------------- */
+#define MLP_BF16 0   /* matrix-product operands in bfloat16, FP32 accumulation */
+#define MLP_FP32 1   /* FP32 operands (used to check gradients)                 */
+
+/* Set (params != NULL) or remove (params == NULL) the preconditioner.
+ * params: host FP32, layer by layer W_l [dims[l]][dims[l+1]] row-major then
+ * b_l [dims[l+1]]; dims: nlayers + 1 widths with dims[0] = 8 Nc^2 + 4 and
+ * dims[nlayers] = 8 Nc^2.  The operator keeps its own copy.                 */
+int nmuller_set_preconditioner(nmuller_t nm, const float* params, const int* dims, int nlayers,
+                               int dtype);
+
+/* z = M(v) for nvec vectors: v, z device [nvec][4][n] complex FP64, z must
+ * not alias v.  IFGF_ENOTPLANNED without a preconditioner.                  */
+int nmuller_precond_apply(nmuller_t nm, const void* v, void* z, int nvec, void* stream);
+
+/* Training rows from (residual, error) pairs in the layout M uses:
+ *  R, E  device [npairs][4][n] complex FP64 (residuals r = A e and errors e)
+ *  X     device FP32 [npairs * P][8 Nc^2 + 4]: pack(r / rms(r)) and features
+ *  T     device FP32 [npairs * P][8 Nc^2]: pack((e - D^-1 r) / rms(r))
+ * Needs a preconditioner set (it fixes the layout; its weights are unused). */
+int nmuller_precond_pairs(nmuller_t nm, const void* R, const void* E, int npairs, float* X,
+                          float* T, void* stream);
+
+/* Host copy of the 4 features of each patch, [P][4] FP32.                  */
+int nmuller_patch_features(nmuller_t nm, float* buf, int64_t cap);
+
+/* The network itself, for training: y = W_L^T .. relu(W_1^T x + b_1) .. + b_L.
+ * All matrix products run on the matrix cores; parameters, gradients and
+ * Adam moments are FP32 (the BF16 form keeps a rounded operand copy of the
+ * weights, refreshed after every update).                                   */
+typedef struct mlp_s* mlp_t;
+
+/* nlayers in [1, 16]; dims: nlayers + 1 widths in [1, 65536]; dtype MLP_BF16
+ * or MLP_FP32; max_batch: largest batch (rows) of any call.  Parameters start
+ * at zero.                                                                  */
+int mlp_create(mlp_t* out, int nlayers, const int* dims, int dtype, int max_batch);
+int mlp_num_params(mlp_t net, int64_t* n);
+/* Host FP32 parameters in the layout of nmuller_set_preconditioner; resets
+ * the Adam state.  Synchronises the device.                                 */
+int mlp_set_params(mlp_t net, const float* params);
+int mlp_get_params(mlp_t net, float* params, void* stream);   /* host FP32, syncs */
+int mlp_get_grad(mlp_t net, float* grad, void* stream);       /* host FP32, syncs */
+/* Y = net(X): X device FP32 [B][dims[0]], Y device FP32 [B][dims[L]],
+ * 1 <= B <= max_batch.  Keeps the activations (and, in FP32, a reference to
+ * X, which must stay unchanged until mlp_backward) for a backward pass.     */
+int mlp_forward(mlp_t net, const float* X, int B, float* Y, void* stream);
+/* Gradients of a loss given dY = dLoss/dY (device FP32 [B][dims[L]]) for the
+ * batch of the preceding mlp_forward: parameter gradient kept in the network
+ * (mlp_get_grad), input gradient written to dX (device [B][dims[0]]) unless
+ * dX is NULL.                                                                */
+int mlp_backward(mlp_t net, const float* dY, int B, float* dX, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with step size lr.      */
+int mlp_adam_step(mlp_t net, float lr, void* stream);
+/* One training step on rows idx[0..B) of X (device FP32 [*][dims[0]]) and
+ * targets T (device FP32 [*][dims[L]]): forward, mean-squared loss (written
+ * to loss, device FP32 [1], before the update), backward, Adam.            */
+int mlp_train_step(mlp_t net, const float* X, const float* T, const int32_t* idx, int B, float lr,
+                   float* loss, void* stream);
+void mlp_destroy(mlp_t net);
 
 /* The IFGF plan used by the operator (owned by nm).                         */
 ifgf_plan_t nmuller_ifgf(nmuller_t nm);

@@ -38,7 +38,8 @@ class NMullerParams(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("true_relres", C.c_double),
-                ("arnoldi_relres", C.c_double), ("seconds", C.c_double)]
+                ("arnoldi_relres", C.c_double), ("seconds", C.c_double),
+                ("precond_iters", C.c_int), ("fallbacks", C.c_int)]
 
 
 _lib = None
@@ -80,13 +81,34 @@ def lib():
         L.nmuller_corrections.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
         L.nmuller_solve.argtypes = [vp, vp, ci, vp, ci, dbl, ci, ci, C.POINTER(SolveInfo), vp]
         L.nmuller_solve.restype = ci
+        L.nmuller_solve_trajectory.argtypes = [vp, vp, vp, dbl, ci, ci, vp, vp, ci, C.POINTER(ci),
+                                               C.POINTER(SolveInfo), vp]
+        L.nmuller_solve_trajectory.restype = ci
+        L.nmuller_set_preconditioner.argtypes = [vp, vp, vp, ci, ci]
+        L.nmuller_precond_apply.argtypes = [vp, vp, vp, ci, vp]
+        L.nmuller_precond_pairs.argtypes = [vp, vp, vp, ci, vp, vp, vp]
+        L.nmuller_patch_features.argtypes = [vp, vp, i64]
+        L.mlp_create.argtypes = [C.POINTER(vp), ci, vp, ci, ci]
+        L.mlp_num_params.argtypes = [vp, C.POINTER(i64)]
+        L.mlp_set_params.argtypes = [vp, vp]
+        L.mlp_get_params.argtypes = [vp, vp, vp]
+        L.mlp_get_grad.argtypes = [vp, vp, vp]
+        L.mlp_forward.argtypes = [vp, vp, ci, vp, vp]
+        L.mlp_backward.argtypes = [vp, vp, ci, vp, vp]
+        L.mlp_adam_step.argtypes = [vp, C.c_float, vp]
+        L.mlp_train_step.argtypes = [vp, vp, vp, vp, ci, C.c_float, vp, vp]
+        L.mlp_destroy.argtypes = [vp]
+        L.mlp_destroy.restype = None
         L.nmuller_ifgf.argtypes = [vp]
         L.nmuller_ifgf.restype = vp
         L.nmuller_destroy.argtypes = [vp]
         L.nmuller_destroy.restype = None
         for name in ("ifgf_plan", "ifgf_apply", "ifgf_plan_counts", "ifgf_plan_table", "ifgf_stats",
                      "nmuller_plan", "nmuller_apply", "nmuller_rhs", "nmuller_geometry",
-                     "nmuller_corrections"):
+                     "nmuller_corrections", "nmuller_set_preconditioner", "nmuller_precond_apply",
+                     "nmuller_precond_pairs", "nmuller_patch_features", "mlp_create", "mlp_num_params",
+                     "mlp_set_params", "mlp_get_params", "mlp_get_grad", "mlp_forward", "mlp_backward",
+                     "mlp_adam_step", "mlp_train_step"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -295,8 +317,133 @@ def nmuller_solve(nm, rhs, nrhs, y, use_x0=False, rtol=1e-4, maxit=500, restart=
     _check(lib().nmuller_solve(nm, rhs.data_ptr(), int(nrhs), y.data_ptr(), int(bool(use_x0)),
                                float(rtol), int(maxit), int(restart), info, _stream_ptr(stream)),
            "nmuller_solve")
-    return [{"iters": i.iters, "converged": bool(i.converged), "true_relres": i.true_relres,
-             "arnoldi_relres": i.arnoldi_relres, "seconds": i.seconds} for i in info]
+    return [_info_dict(i) for i in info]
+
+
+def _info_dict(i):
+    return {"iters": i.iters, "converged": bool(i.converged), "true_relres": i.true_relres,
+            "arnoldi_relres": i.arnoldi_relres, "seconds": i.seconds,
+            "precond_iters": i.precond_iters, "fallbacks": i.fallbacks}
+
+
+def nmuller_solve_trajectory(nm, rhs, y, X, R, rtol=1e-4, maxit=500, stride=1, stream=None):
+    """Unrestarted GMRES from 0 recording (x_k, r_k) every `stride` iterations
+    into X, R (device [cap][4][n] complex128).  Returns (count, info dict)."""
+    info = SolveInfo()
+    nrec = C.c_int(0)
+    _check(lib().nmuller_solve_trajectory(nm, rhs.data_ptr(), y.data_ptr(), float(rtol), int(maxit),
+                                          int(stride), X.data_ptr(), R.data_ptr(), int(X.shape[0]),
+                                          C.byref(nrec), C.byref(info), _stream_ptr(stream)),
+           "nmuller_solve_trajectory")
+    return nrec.value, _info_dict(info)
+
+
+MLP_BF16 = 0
+MLP_FP32 = 1
+
+
+def _dims_arr(dims):
+    return (C.c_int * len(dims))(*[int(d) for d in dims])
+
+
+def nmuller_set_preconditioner(nm, params, dims, dtype=MLP_BF16):
+    if params is None:
+        _check(lib().nmuller_set_preconditioner(nm, None, None, 0, int(dtype)), "nmuller_set_preconditioner")
+        return
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    _check(lib().nmuller_set_preconditioner(nm, p.ctypes.data, _dims_arr(dims), len(dims) - 1, int(dtype)),
+           "nmuller_set_preconditioner")
+
+
+def nmuller_precond_apply(nm, v, z, stream=None):
+    """v, z: device [nvec][4][n] complex128."""
+    _check(lib().nmuller_precond_apply(nm, v.data_ptr(), z.data_ptr(), int(v.shape[0]), _stream_ptr(stream)),
+           "nmuller_precond_apply")
+
+
+def nmuller_precond_pairs(nm, R, E, X, T, stream=None):
+    """R, E: device [npairs][4][n] complex128; X, T: device float32 rows."""
+    _check(lib().nmuller_precond_pairs(nm, R.data_ptr(), E.data_ptr(), int(R.shape[0]), X.data_ptr(),
+                                       T.data_ptr(), _stream_ptr(stream)), "nmuller_precond_pairs")
+
+
+def nmuller_patch_features(nm, P):
+    out = np.zeros((P, 4), dtype=np.float32)
+    _check(lib().nmuller_patch_features(nm, out.ctypes.data, out.size), "nmuller_patch_features")
+    return out
+
+
+class MLP:
+    """Owning wrapper around an mlp_t network (device-resident)."""
+
+    def __init__(self, dims, dtype=MLP_BF16, max_batch=1024):
+        self.dims = [int(d) for d in dims]
+        self.dtype = int(dtype)
+        self.max_batch = int(max_batch)
+        h = C.c_void_p()
+        _check(lib().mlp_create(C.byref(h), len(dims) - 1, _dims_arr(dims), self.dtype, self.max_batch),
+               "mlp_create")
+        self.handle = h.value
+        n = C.c_int64()
+        _check(lib().mlp_num_params(self.handle, C.byref(n)), "mlp_num_params")
+        self.n_params = n.value
+
+    def set_params(self, theta):
+        p = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        _check(lib().mlp_set_params(self.handle, p.ctypes.data), "mlp_set_params")
+
+    def params(self, stream=None):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().mlp_get_params(self.handle, out.ctypes.data, _stream_ptr(stream)), "mlp_get_params")
+        return out
+
+    def grad(self, stream=None):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().mlp_get_grad(self.handle, out.ctypes.data, _stream_ptr(stream)), "mlp_get_grad")
+        return out
+
+    def _f32(self, t, cols):
+        import torch
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.shape[-1] != cols:
+            raise ValueError(f"expected a contiguous float32 device tensor with {cols} columns")
+        return t
+
+    def forward(self, X, Y=None, stream=None):
+        import torch
+        X = self._f32(X, self.dims[0])
+        if Y is None:
+            Y = torch.empty((X.shape[0], self.dims[-1]), dtype=torch.float32, device=X.device)
+        _check(lib().mlp_forward(self.handle, X.data_ptr(), int(X.shape[0]), Y.data_ptr(), _stream_ptr(stream)),
+               "mlp_forward")
+        return Y
+
+    def backward(self, dY, dX=None, stream=None):
+        dY = self._f32(dY, self.dims[-1])
+        _check(lib().mlp_backward(self.handle, dY.data_ptr(), int(dY.shape[0]),
+                                  dX.data_ptr() if dX is not None else None, _stream_ptr(stream)),
+               "mlp_backward")
+        return dX
+
+    def adam_step(self, lr, stream=None):
+        _check(lib().mlp_adam_step(self.handle, float(lr), _stream_ptr(stream)), "mlp_adam_step")
+
+    def train_step(self, X, T, idx, lr, loss, stream=None):
+        """idx: device int32 [B]; loss: device float32 [1]."""
+        _check(lib().mlp_train_step(self.handle, X.data_ptr(), T.data_ptr(), idx.data_ptr(), int(idx.shape[0]),
+                                    float(lr), loss.data_ptr(), _stream_ptr(stream)), "mlp_train_step")
+
+    def close(self):
+        if self.handle:
+            lib().mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def nmuller_destroy(nm):
@@ -345,6 +492,33 @@ class NMullerOperator:
 
     def corrections(self, values=True):
         return nmuller_corrections(self.handle, self.n, self.Nc, values)
+
+    def solve_trajectory(self, b, X, R, rtol=1e-4, maxit=500, stride=1, stream=None):
+        import torch
+        y = torch.empty_like(b[0] if b.dim() == 3 else b)
+        cnt, info = nmuller_solve_trajectory(self.handle, b.contiguous(), y, X, R, rtol, maxit, stride, stream)
+        return y, cnt, info
+
+    def set_preconditioner(self, params, dims=None, dtype=MLP_BF16):
+        nmuller_set_preconditioner(self.handle, params, dims, dtype)
+
+    def precond_apply(self, v, z=None, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(v)
+        nmuller_precond_apply(self.handle, v, z, stream)
+        return z
+
+    def precond_pairs(self, R, E, stream=None):
+        import torch
+        npairs, nq = R.shape[0], self.Nc * self.Nc
+        X = torch.empty((npairs * self.P, 8 * nq + 4), dtype=torch.float32, device=R.device)
+        T = torch.empty((npairs * self.P, 8 * nq), dtype=torch.float32, device=R.device)
+        nmuller_precond_pairs(self.handle, R, E, X, T, stream)
+        return X, T
+
+    def patch_features(self):
+        return nmuller_patch_features(self.handle, self.P)
 
     def ifgf_handle(self):
         return lib().nmuller_ifgf(self.handle)

@@ -6,6 +6,8 @@
 // derivatives via Chebyshev recurrences); Sec. III-H (local corrections).
 #include <hip/hip_runtime.h>
 
+#include <memory>
+
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -14,6 +16,7 @@
 #include "../../include/ifgf.h"
 #include "device.hpp"
 #include "nmuller_host.hpp"
+#include "precond.hpp"
 #include "util.hpp"
 
 using namespace ifgf;
@@ -268,10 +271,13 @@ struct nmuller_s {
   double2* d_phi = nullptr;   // [max_nrhs][8][n]
   double2* d_sd = nullptr;    // [max_nrhs][2][14][n]
   Mat mat{};
+  std::unique_ptr<ifgf::Precond> pc;   // learned preconditioner (optional)
   ~nmuller_s() {
     if (ifgf) ifgf_destroy(ifgf);
   }
 };
+
+ifgf::Precond* nmuller_precond(nmuller_s* nm) { return nm ? nm->pc.get() : nullptr; }
 
 namespace {
 template <class T>
@@ -457,6 +463,62 @@ int nmuller_corrections(nmuller_t nm, int64_t* npairs, int64_t* row_off, int32_t
     if (nm->cor.vals.empty()) return set_error(IFGF_ENOTPLANNED, "values are kept only by host_only plans");
     std::memcpy(vals, nm->cor.vals.data(), nm->cor.vals.size() * sizeof(double));
   }
+  return IFGF_OK;
+}
+
+int nmuller_set_preconditioner(nmuller_t nm, const float* params, const int* dims, int nlayers, int dtype) {
+  clear_error();
+  if (!nm) return set_error(IFGF_EINVAL, "null argument");
+  if (nm->host_only) return set_error(IFGF_ENOTPLANNED, "plan was built with host_only");
+  nm->pc.reset();
+  if (!params) return IFGF_OK;
+  std::unique_ptr<ifgf::Precond> pc(new (std::nothrow) ifgf::Precond());
+  if (!pc) return set_error(IFGF_ENOMEM, "host allocation failed");
+  const nmuller_params& p = nm->prm;
+  std::vector<float> feat = ifgf::patch_features(p.P, p.Nc, nm->geo.x.data(), nm->geo.nrm.data(), nm->mat.ke,
+                                                 nm->mat.ki, p.eps_i / p.eps_e);
+  int rc = ifgf::precond_create(*pc, p.P, p.Nc, feat, 2.0 / (p.mu_e + p.mu_i), 2.0 / (p.eps_e + p.eps_i),
+                                params, dims, nlayers, dtype);
+  if (rc) return rc;
+  nm->pc = std::move(pc);
+  return IFGF_OK;
+}
+
+int nmuller_precond_apply(nmuller_t nm, const void* v, void* z, int nvec, void* stream) {
+  clear_error();
+  if (!nm || !v || !z) return set_error(IFGF_EINVAL, "null argument");
+  if (!nm->pc) return set_error(IFGF_ENOTPLANNED, "no preconditioner set");
+  if (nvec < 1) return set_error(IFGF_EINVAL, "nvec must be >= 1");
+  if (v == z) return set_error(IFGF_EINVAL, "z must not alias v");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t m = 4 * nm->gd.n;
+  for (int i = 0; i < nvec; ++i) {
+    hipError_t e = ifgf::precond_apply(*nm->pc, static_cast<const double2*>(v) + i * m,
+                                       static_cast<double2*>(z) + i * m, st);
+    if (e != hipSuccess) return set_hip_error(e, "preconditioner apply");
+  }
+  return IFGF_OK;
+}
+
+int nmuller_precond_pairs(nmuller_t nm, const void* R, const void* E, int npairs, float* X, float* T,
+                          void* stream) {
+  clear_error();
+  if (!nm || !R || !E || !X || !T) return set_error(IFGF_EINVAL, "null argument");
+  if (!nm->pc) return set_error(IFGF_ENOTPLANNED, "no preconditioner set (it fixes the feature layout)");
+  if (npairs < 1) return set_error(IFGF_EINVAL, "npairs must be >= 1");
+  hipError_t e = ifgf::precond_pairs(*nm->pc, static_cast<const double2*>(R), static_cast<const double2*>(E),
+                                     npairs, X, T, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? IFGF_OK : set_hip_error(e, "preconditioner pairs");
+}
+
+int nmuller_patch_features(nmuller_t nm, float* buf, int64_t cap) {
+  clear_error();
+  if (!nm || !buf) return set_error(IFGF_EINVAL, "null argument");
+  const nmuller_params& p = nm->prm;
+  std::vector<float> f = ifgf::patch_features(p.P, p.Nc, nm->geo.x.data(), nm->geo.nrm.data(), nm->mat.ke,
+                                              nm->mat.ki, p.eps_i / p.eps_e);
+  if (cap < (int64_t)f.size()) return set_error(IFGF_EINVAL, "buffer too small");
+  std::memcpy(buf, f.data(), f.size() * sizeof(float));
   return IFGF_OK;
 }
 
