@@ -1,5 +1,6 @@
 #!/usr/bin/env python
-"""Throughput of the IFGF-accelerated N-Mueller forward map on one MI355X.
+"""Throughput of the IFGF-accelerated N-Mueller forward map on one MI355X,
+and GMRES time to a 1e-4 true residual.
 
 Workload (default): a dielectric sphere of radius 5 (10 vacuum wavelengths
 across; eps_r = 2.25 inside, vacuum outside: k_int = 3 pi, k_ext = 2 pi),
@@ -9,13 +10,21 @@ nodes (153,600 points, 614,400 unknowns), IFGF tolerance 1e-4.
 A step is one N-Mueller matrix-vector product A y (densities, IFGF sums of
 S and n.grad S for 8 densities x 2 wavenumbers, near-field corrections,
 operator assembly) on i.i.d. complex normal unknowns, everything resident
-in HBM before the timed region.  After the timed steps one GMRES solve of a
-plane-wave right-hand side (+z, polarised x) to a 1e-4 true residual is
-timed as well.  Prints one JSON line.
+in HBM before the timed region.  The headline form is the mixed one: IFGF
+cone grids and interpolation in FP32, corrections, assembly and GMRES in
+FP64.  The plain FP64 form of the same operator is timed beside it.
+
+After the timed steps, GMRES solves of a plane-wave right-hand side (+z,
+polarised x) to a 1e-4 true FP64 residual: mixed, FP64, flexible GMRES with
+the identity-part scaling D^-1, and flexible GMRES with the learned
+preconditioner (trained parameters from paper_2408_02274_amd/weights).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -26,10 +35,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "IFGF N-Müller matvecs/s + GMRES time-to-1e-4 residual, mixed/learned vs FP64"
+WEIGHTS = os.path.join(ROOT, "paper_2408_02274_amd", "weights", "precond_nc10.npz")
+TRAFFIC = os.path.join(ROOT, "profiles", "propagate_fp32_sphere153k_hbm_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2408_02274_amd", "csrc", "ifgf_mfma.hip")
 
 
 def flops_per_unit(name, npts):
-    """Algorithmic flops per work unit (FMA = 2 flops, transcendental = 1)."""
+    """Algorithmic flops per work unit (FMA = 2 flops, transcendental = 1,
+    real x complex multiply-add = 4)."""
     return {
         "near": 280.0,                                   # (target, source) pair, 2 wavenumbers
         "leaf": 160.0,                                   # (interpolation point, source) pair
@@ -43,7 +56,33 @@ def bytes_per_unit(name):
     return {"nm_correct": 68.0}.get(name, 0.0)
 
 
-PEAK = {"fp64_valu": 78.6e12, "fp32_valu_nopk": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
+PEAK = {"fp64": 78.6e12, "fp32_valu_nopk": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
+
+
+def kernel_sha(path=KERNEL_SRC):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_per_launch(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none for this kernel and precision or the
+    kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    vals = {}
+    for line in open(TRAFFIC):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel") != kernel or vals.get("precision") != precision:
+        return None
+    if vals.get("kernel_source_sha256") != kernel_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(surface, ks, w, sample_rows, seed=2):
@@ -66,18 +105,31 @@ def cpu_baseline(surface, ks, w, sample_rows, seed=2):
                       f"O(N), are left out in the oracle's favour)"}
 
 
+def kernel_table(st, steps, npts):
+    kern = {}
+    for name, t in st.get("timing", {}).items():
+        kern[name] = {"launches": t["launches"], "ms": t["ms"],
+                      "flop": flops_per_unit(name, npts) * t["units"],
+                      "bytes": bytes_per_unit(name) * t["units"]}
+    return kern
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
+                    help="IFGF form of the timed steps: fp32 = mixed (default), fp64 = plain")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--npf", type=int, default=16, help="patches per cube face edge")
     ap.add_argument("--radius", type=float, default=5.0)
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-fp64-gmres", action="store_true", help="skip the FP64-form GMRES solve")
+    ap.add_argument("--maxit", type=int, default=400)
+    ap.add_argument("--no-fp64-form", action="store_true", help="skip timing the FP64 form beside the mixed one")
     ap.add_argument("--ifgf-only", action="store_true",
                     help="time the raw IFGF sums only (no N-Mueller plan: seconds to set up)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -109,7 +161,8 @@ def main():
 
     surf = synth.cube_sphere(args.npf, 10, args.radius)
     eps_e, eps_i = 1.0, 2.25
-    prec = B.IFGF_FP64 if args.precision == "fp64" else B.IFGF_FP32
+    fp32 = args.precision == "fp32"
+    prec = B.IFGF_FP32 if fp32 else B.IFGF_FP64
     t0 = time.perf_counter()
     if args.ifgf_only:
         from paper_2408_02274_amd import IFGFPlan
@@ -128,78 +181,123 @@ def main():
     plan_s = time.perf_counter() - t0
     log(f"plan built in {plan_s:.1f} s (n = {surf.n})")
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        op.apply(y, out)
-    torch.cuda.synchronize()
-    log("warmup done")
-    B.ifgf_set_timing(ih, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        op.apply(y, out, stream=stream.cuda_stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    st = B.ifgf_stats(ih)
-    B.ifgf_set_timing(ih, False)
-    log(f"{args.steps} matvecs in {elapsed:.3f} s")
+
+    def timed_steps(steps, warmup):
+        for _ in range(warmup):
+            op.apply(y, out, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        B.ifgf_set_timing(ih, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            op.apply(y, out, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = B.ifgf_stats(ih)
+        B.ifgf_set_timing(ih, False)
+        return el, st
+
+    elapsed, st = timed_steps(args.steps, args.warmup)
+    log(f"{args.steps} matvecs ({args.precision}) in {elapsed:.3f} s")
     ms_per_step = elapsed / args.steps * 1e3
     value = args.steps / elapsed
-
     npts = st["Ps"] * st["Pa"] * st["Pa"]
-    kern = {}
-    for name, t in st.get("timing", {}).items():
-        kern[name] = {"launches": t["launches"], "ms": t["ms"],
-                      "flop": flops_per_unit(name, npts) * t["units"],
-                      "bytes": bytes_per_unit(name) * t["units"]}
+    kern = kernel_table(st, args.steps, npts)
+    out_main = out.clone()
+
+    # the plain FP64 form of the same operator, and the mixed form's deviation from it
+    fp64_form = None
+    if fp32 and not args.no_fp64_form:
+        B.ifgf_set_precision(ih, B.IFGF_FP64)
+        el64, st64 = timed_steps(max(1, min(args.steps, 3)), 1)
+        n64 = max(1, min(args.steps, 3))
+        dev = float(torch.linalg.norm(out_main - out) / torch.linalg.norm(out))
+        B.ifgf_set_precision(ih, B.IFGF_FP32)
+        k64 = kernel_table(st64, n64, npts)
+        fp64_form = {"matvecs_per_s": n64 / el64, "ms_per_step": el64 / n64 * 1e3,
+                     "speedup_mixed_over_fp64": value / (n64 / el64),
+                     "mixed_vs_fp64_rel_l2": dev,
+                     "kernels_ms_per_step": {k: round(v["ms"] / n64, 4) for k, v in k64.items()}}
+        log(f"FP64 form: {fp64_form['ms_per_step']:.1f} ms/step; mixed deviates by {dev:.2e}")
+
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
+    avg_launch_s = d["ms"] * 1e-3 / d["launches"]
     if d["flop"] > 0:
         achieved = d["flop"] / (d["ms"] * 1e-3)
         mfma = dom in ("propagate",)          # contraction on the matrix cores
         if mfma:
-            peak = PEAK["fp64_valu"] if args.precision == "fp64" else PEAK["fp32_mfma"]
+            peak = PEAK["fp32_mfma"] if fp32 else PEAK["fp64"]
         else:
-            peak = PEAK["fp64_valu"] if args.precision == "fp64" else PEAK["fp32_valu_nopk"]
+            peak = PEAK["fp32_valu_nopk"] if fp32 else PEAK["fp64"]
         roof = {"bound": "mfma" if mfma else "alu", "kernel": dom, "achieved": achieved / 1e12,
-                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak}
     else:
         achieved = d["bytes"] / (d["ms"] * 1e-3)
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": 8000.0,
-                "unit": "GB/s", "frac": achieved / PEAK["hbm"], "traffic": None}
-    roof["avg_launch_ms"] = d["ms"] / d["launches"]
+                "unit": "GB/s", "frac": achieved / PEAK["hbm"]}
+    tr = traffic_per_launch(dom, args.precision)
+    roof["traffic"] = tr
+    if tr is not None:
+        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roof["traffic_GBps"] = tr / avg_launch_s / 1e9
+    roof["avg_launch_ms"] = avg_launch_s * 1e3
+    roof["flop_per_launch"] = d["flop"] / d["launches"]
 
     gm = None
     if not args.no_gmres:
-        nm_geo = synth.cube_sphere(args.npf, 10, args.radius)
         ke = 2 * math.pi * math.sqrt(eps_e)
-        ph = np.exp(1j * ke * nm_geo.x[:, 2])
+        ph = np.exp(1j * ke * surf.x[:, 2])
         E = np.zeros((1, surf.n, 3), complex)
         H = np.zeros_like(E)
         E[0, :, 0] = ph
         H[0, :, 1] = (ke / (2 * math.pi)) * ph
         b = op.rhs(torch.from_numpy(E).to("cuda"), torch.from_numpy(H).to("cuda"))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ysol, info = op.solve(b, rtol=1e-4, maxit=400)
-        torch.cuda.synchronize()
-        gm = {"seconds": time.perf_counter() - t0, "iters": info[0]["iters"],
-              "true_relres": info[0]["true_relres"], "converged": info[0]["converged"]}
-        log(f"GMRES {gm}")
+        gm = {}
+
+        def solve(tag):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ysol, info = op.solve(b, rtol=1e-4, maxit=args.maxit)
+            torch.cuda.synchronize()
+            r = {"seconds": time.perf_counter() - t0, "iters": info[0]["iters"],
+                 "true_relres": info[0]["true_relres"], "converged": info[0]["converged"],
+                 "precond_iters": info[0]["precond_iters"], "fallbacks": info[0]["fallbacks"]}
+            log(f"GMRES {tag}: {r}")
+            gm[tag] = r
+
+        solve("mixed" if fp32 else "fp64")
+        if fp32 and not args.no_fp64_gmres:
+            B.ifgf_set_precision(ih, B.IFGF_FP64)
+            solve("fp64")
+            B.ifgf_set_precision(ih, B.IFGF_FP32)
+        nq = surf.nc * surf.nc
+        dims = [8 * nq + 4, 256, 256, 8 * nq]
+        nparams = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+        op.set_preconditioner(np.zeros(nparams, np.float32), dims)
+        solve("scaling_only" + ("_mixed" if fp32 else ""))
+        if os.path.exists(WEIGHTS):
+            z = np.load(WEIGHTS)
+            op.set_preconditioner(z["params"], [int(v) for v in z["dims"]])
+            solve("learned" + ("_mixed" if fp32 else ""))
+        op.set_preconditioner(None)
 
     res = {
         "metric": METRIC, "value": value, "unit": "matvecs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": ("IFGF raw sums only: " if args.ifgf_only else "") +
                                f"N-Mueller forward map, dielectric sphere radius {args.radius} "
                                f"(eps_r 2.25 in vacuum, k_int = 3 pi, k_ext = 2 pi), 6x{args.npf}x{args.npf} "
                                f"patches x 10x10 Chebyshev nodes ({surf.n} points, {4 * surf.n} unknowns), "
-                               f"IFGF tol {args.tol}, 1 RHS",
+                               f"IFGF tol {args.tol}, 1 RHS, "
+                               + ("mixed: FP32 IFGF, FP64 corrections/assembly/GMRES" if fp32 else "FP64"),
                    "Ps": st["Ps"], "Pa": st["Pa"], "D": st["D"], "plan_seconds": round(plan_s, 2),
                    "precision": args.precision},
-        "gmres_time_to_1e-4_s": gm["seconds"] if gm else None,
+        "fp64_form": fp64_form,
+        "gmres_time_to_1e-4_s": (gm.get("mixed") or gm.get("fp64"))["seconds"] if gm else None,
         "gmres": gm,
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in kern.items()},
