@@ -105,6 +105,44 @@ def cpu_baseline(surface, ks, w, sample_rows, seed=2):
                       f"O(N), are left out in the oracle's favour)"}
 
 
+def batching(log, reps=5):
+    """64 random right-hand sides on the unit sphere (24 patches x 8 x 8
+    nodes, k_ext = 2 pi, eps_r 2.25): one-at-a-time applies, one batched
+    apply (column batch chosen by the autotuner), and one graph launch of the
+    batched apply."""
+    import torch
+    import synth
+    from paper_2408_02274_amd import NMullerGraph, NMullerOperator
+    from paper_2408_02274_amd import binding as B
+    s = synth.cube_sphere(2, 8, 1.0)
+    op = NMullerOperator(s, 1.0, 2.25, tol=1e-4, precision=B.IFGF_FP32, max_nrhs=64, batch_columns=4)
+    cols = B.ifgf_autotune(op.ifgf_handle())
+    y = torch.from_numpy(synth.complex_normal((64, 4, s.n), 3)).to("cuda")
+    out = torch.empty_like(y)
+
+    def clock(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_loop = clock(lambda: [op.apply(y[r:r + 1], out[r:r + 1]) for r in range(64)])
+    t_batch = clock(lambda: op.apply(y, out))
+    g = NMullerGraph([op], [y], [out])
+    t_graph = clock(g.launch)
+    res = {"workload": "config-1 sphere (1,536 points), 64 RHS, mixed form",
+           "rhs_matvecs_per_s_looped": 64 / t_loop, "rhs_matvecs_per_s_batched": 64 / t_batch,
+           "rhs_matvecs_per_s_graph": 64 / t_graph, "graph_nodes": g.nodes, "autotuned_columns": cols,
+           "ms_looped": t_loop * 1e3, "ms_batched": t_batch * 1e3, "ms_graph": t_graph * 1e3}
+    g.close()
+    op.close()
+    log(f"batching: {res}")
+    return res
+
+
 def kernel_table(st, steps, npts):
     kern = {}
     for name, t in st.get("timing", {}).items():
@@ -118,18 +156,21 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides per step (stacked into the cone-data columns)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
                     help="IFGF form of the timed steps: fp32 = mixed (default), fp64 = plain")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--npf", type=int, default=16, help="patches per cube face edge")
     ap.add_argument("--radius", type=float, default=5.0)
-    ap.add_argument("--cpu-rows", type=int, default=384)
+    ap.add_argument("--cpu-rows", type=int, default=1536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-fp64-gmres", action="store_true", help="skip the FP64-form GMRES solve")
     ap.add_argument("--maxit", type=int, default=400)
     ap.add_argument("--no-fp64-form", action="store_true", help="skip timing the FP64 form beside the mixed one")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-RHS batching measurement")
     ap.add_argument("--ifgf-only", action="store_true",
                     help="time the raw IFGF sums only (no N-Mueller plan: seconds to set up)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -168,15 +209,15 @@ def main():
         from paper_2408_02274_amd import IFGFPlan
         ks = (2 * math.pi * math.sqrt(eps_i), 2 * math.pi * math.sqrt(eps_e))
         w = np.full(surf.n, 4.0 * math.pi * args.radius ** 2 / surf.n)
-        op = IFGFPlan(surf.x, surf.normal, w, ks[0], ks[1], args.tol, precision=prec)
+        op = IFGFPlan(surf.x, surf.normal, w, ks[0], ks[1], args.tol, precision=prec, max_nrhs=args.nrhs)
         ih = op.handle
-        y = torch.from_numpy(synth.complex_normal((1, 8, surf.n), 2)).to("cuda")
-        out = torch.empty((1, 2, 14, surf.n), dtype=torch.complex128, device="cuda")
+        y = torch.from_numpy(synth.complex_normal((args.nrhs, 8, surf.n), 2)).to("cuda")
+        out = torch.empty((args.nrhs, 2, 14, surf.n), dtype=torch.complex128, device="cuda")
         args.no_gmres = True
     else:
-        op = NMullerOperator(surf, eps_e, eps_i, tol=args.tol, precision=prec)
+        op = NMullerOperator(surf, eps_e, eps_i, tol=args.tol, precision=prec, max_nrhs=args.nrhs)
         ih = op.ifgf_handle()
-        y = torch.from_numpy(synth.complex_normal((1, 4, surf.n), 2)).to("cuda")
+        y = torch.from_numpy(synth.complex_normal((args.nrhs, 4, surf.n), 2)).to("cuda")
         out = torch.empty_like(y)
     plan_s = time.perf_counter() - t0
     log(f"plan built in {plan_s:.1f} s (n = {surf.n})")
@@ -200,7 +241,7 @@ def main():
     elapsed, st = timed_steps(args.steps, args.warmup)
     log(f"{args.steps} matvecs ({args.precision}) in {elapsed:.3f} s")
     ms_per_step = elapsed / args.steps * 1e3
-    value = args.steps / elapsed
+    value = args.steps * args.nrhs / elapsed
     npts = st["Ps"] * st["Pa"] * st["Pa"]
     kern = kernel_table(st, args.steps, npts)
     out_main = out.clone()
@@ -214,8 +255,8 @@ def main():
         dev = float(torch.linalg.norm(out_main - out) / torch.linalg.norm(out))
         B.ifgf_set_precision(ih, B.IFGF_FP32)
         k64 = kernel_table(st64, n64, npts)
-        fp64_form = {"matvecs_per_s": n64 / el64, "ms_per_step": el64 / n64 * 1e3,
-                     "speedup_mixed_over_fp64": value / (n64 / el64),
+        fp64_form = {"matvecs_per_s": n64 * args.nrhs / el64, "ms_per_step": el64 / n64 * 1e3,
+                     "speedup_mixed_over_fp64": value / (n64 * args.nrhs / el64),
                      "mixed_vs_fp64_rel_l2": dev,
                      "kernels_ms_per_step": {k: round(v["ms"] / n64, 4) for k, v in k64.items()}}
         log(f"FP64 form: {fp64_form['ms_per_step']:.1f} ms/step; mixed deviates by {dev:.2e}")
@@ -292,7 +333,7 @@ def main():
                                f"N-Mueller forward map, dielectric sphere radius {args.radius} "
                                f"(eps_r 2.25 in vacuum, k_int = 3 pi, k_ext = 2 pi), 6x{args.npf}x{args.npf} "
                                f"patches x 10x10 Chebyshev nodes ({surf.n} points, {4 * surf.n} unknowns), "
-                               f"IFGF tol {args.tol}, 1 RHS, "
+                               f"IFGF tol {args.tol}, {args.nrhs} RHS per step, "
                                + ("mixed: FP32 IFGF, FP64 corrections/assembly/GMRES" if fp32 else "FP64"),
                    "Ps": st["Ps"], "Pa": st["Pa"], "D": st["D"], "plan_seconds": round(plan_s, 2),
                    "precision": args.precision},
@@ -302,6 +343,8 @@ def main():
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in kern.items()},
     }
+    if not args.no_batch and not args.ifgf_only:
+        res["batching"] = batching(log)
     if not args.no_cpu:
         ks = (2 * math.pi * math.sqrt(eps_i), 2 * math.pi * math.sqrt(eps_e))
         w = np.full(surf.n, 4.0 * math.pi * args.radius ** 2 / surf.n) if args.ifgf_only else op.geometry(1)

@@ -55,7 +55,11 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  * max_nrhs: largest nrhs accepted by the apply calls (sizes workspaces).
  * host_only: 1 builds the host tables only (no device memory is touched);
  *   such a plan serves ifgf_plan_counts/ifgf_plan_table/ifgf_stats, and the
- *   apply calls return IFGF_ENOTPLANNED.                                    */
+ *   apply calls return IFGF_ENOTPLANNED.
+ * batch_columns: right-hand sides stacked into the columns of one pass of
+ *   the matrix-core kernels (1, 2 or 4; FP64 at most 2; 0 -> 1).  The cone
+ *   buffers grow by that factor; whether it pays depends on the workload
+ *   (ifgf_autotune measures it).                                            */
 typedef struct {
   int Ps, Pa;
   int ns_init, na_init;
@@ -64,6 +68,7 @@ typedef struct {
   int precision;
   int max_nrhs;
   int host_only;
+  int batch_columns;
 } ifgf_options;
 
 void ifgf_default_options(ifgf_options* opt);
@@ -117,6 +122,13 @@ int ifgf_plan_table(ifgf_plan_t plan, int which, int64_t* buf, int64_t cap,
  * units (pairs or points) since timing was switched on.  Reading the timing
  * synchronises on the recorded events.                                     */
 int ifgf_stats(ifgf_plan_t plan, char* json, size_t cap);
+
+/* Time one apply for every column batch R = 1, 2, 4 up to the plan's
+ * min(batch_columns, max_nrhs) (on zero densities, in buffers it allocates
+ * and frees) and keep the R with the lowest time per right-hand side for
+ * the following applies; `chosen` (may be NULL) receives it.  Synchronises
+ * the stream.  Per-kernel timing must be off.                               */
+int ifgf_autotune(ifgf_plan_t plan, void* stream, int* chosen);
 
 /* Switch the working precision of a built plan (IFGF_FP64 or IFGF_FP32)
  * for the following apply calls; `previous` (may be NULL) receives the one
@@ -302,6 +314,27 @@ int mlp_adam_step(mlp_t net, float lr, void* stream);
 int mlp_train_step(mlp_t net, const float* X, const float* T, const int32_t* idx, int B, float lr,
                    float* loss, void* stream);
 void mlp_destroy(mlp_t net);
+
+/* ---------------------------------------------------------------------------
+ * Batching by graph capture (project addition): the applies of several
+ * operators (bodies), each on its own nrhs right-hand sides, recorded once
+ * into one HIP graph and replayed with a single launch.  The apply path
+ * neither allocates nor synchronises, so a replay does exactly the eager
+ * work on the buffers given at capture time (their contents may change
+ * between launches; the buffers themselves must stay allocated).
+ * ------------------------------------------------------------------------- */
+typedef struct ifgf_graph_s* ifgf_graph_t;
+
+/* Capture nmuller_apply(ops[i], y[i], nrhs[i], Ay[i]) for i < nops, in that
+ * order, on a private stream.  y[i], Ay[i] device [nrhs[i]][4][n_i] complex
+ * FP64.  Per-kernel timing must be off on every operator (IFGF_EINVAL).    */
+int nmuller_graph_capture(ifgf_graph_t* out, int nops, const nmuller_t* ops,
+                          const void* const* y, const int* nrhs, void* const* Ay);
+/* Enqueue one replay on `stream`.                                           */
+int ifgf_graph_launch(ifgf_graph_t g, void* stream);
+/* Number of nodes (kernel launches) in the captured graph.                  */
+int ifgf_graph_nodes(ifgf_graph_t g, int64_t* nodes);
+void ifgf_graph_destroy(ifgf_graph_t g);
 
 /* The IFGF plan used by the operator (owned by nm).                         */
 ifgf_plan_t nmuller_ifgf(nmuller_t nm);

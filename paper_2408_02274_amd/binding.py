@@ -27,7 +27,8 @@ class IFGFError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("Ps", C.c_int), ("Pa", C.c_int), ("ns_init", C.c_int), ("na_init", C.c_int),
                 ("refine_radial", C.c_int), ("leaf_wavelengths", C.c_double),
-                ("precision", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int)]
+                ("precision", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int),
+                ("batch_columns", C.c_int)]
 
 
 class NMullerParams(C.Structure):
@@ -67,6 +68,8 @@ def lib():
         L.ifgf_set_timing.argtypes = [vp, ci]
         L.ifgf_set_timing.restype = ci
         L.ifgf_set_precision.argtypes = [vp, ci, C.POINTER(ci)]
+        L.ifgf_autotune.argtypes = [vp, vp, C.POINTER(ci)]
+        L.ifgf_autotune.restype = ci
         L.ifgf_set_precision.restype = ci
         L.ifgf_destroy.argtypes = [vp]
         L.ifgf_destroy.restype = None
@@ -97,6 +100,11 @@ def lib():
         L.mlp_backward.argtypes = [vp, vp, ci, vp, vp]
         L.mlp_adam_step.argtypes = [vp, C.c_float, vp]
         L.mlp_train_step.argtypes = [vp, vp, vp, vp, ci, C.c_float, vp, vp]
+        L.nmuller_graph_capture.argtypes = [C.POINTER(vp), ci, vp, vp, vp, vp]
+        L.ifgf_graph_launch.argtypes = [vp, vp]
+        L.ifgf_graph_nodes.argtypes = [vp, C.POINTER(i64)]
+        L.ifgf_graph_destroy.argtypes = [vp]
+        L.ifgf_graph_destroy.restype = None
         L.mlp_destroy.argtypes = [vp]
         L.mlp_destroy.restype = None
         L.nmuller_ifgf.argtypes = [vp]
@@ -108,7 +116,8 @@ def lib():
                      "nmuller_corrections", "nmuller_set_preconditioner", "nmuller_precond_apply",
                      "nmuller_precond_pairs", "nmuller_patch_features", "mlp_create", "mlp_num_params",
                      "mlp_set_params", "mlp_get_params", "mlp_get_grad", "mlp_forward", "mlp_backward",
-                     "mlp_adam_step", "mlp_train_step"):
+                     "mlp_adam_step", "mlp_train_step", "nmuller_graph_capture", "ifgf_graph_launch",
+                     "ifgf_graph_nodes"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -198,6 +207,13 @@ def ifgf_stats(plan):
 
 def ifgf_set_timing(plan, on):
     _check(lib().ifgf_set_timing(plan, int(bool(on))), "ifgf_set_timing")
+
+
+def ifgf_autotune(plan, stream=None):
+    """Pick the fastest column batch (1, 2 or 4 RHS per pass); returns it."""
+    r = C.c_int(0)
+    _check(lib().ifgf_autotune(plan, _stream_ptr(stream), C.byref(r)), "ifgf_autotune")
+    return r.value
 
 
 def ifgf_set_precision(plan, precision):
@@ -336,6 +352,45 @@ def nmuller_solve_trajectory(nm, rhs, y, X, R, rtol=1e-4, maxit=500, stride=1, s
                                           C.byref(nrec), C.byref(info), _stream_ptr(stream)),
            "nmuller_solve_trajectory")
     return nrec.value, _info_dict(info)
+
+
+class NMullerGraph:
+    """One HIP graph replaying op.apply(y, Ay) for several (op, y, Ay):
+    many bodies and right-hand sides in a single launch.  The tensors are
+    referenced, not copied: keep them alive while the graph exists."""
+
+    def __init__(self, ops, ys, Ays):
+        if not (len(ops) == len(ys) == len(Ays)) or not ops:
+            raise ValueError("need equally many operators, inputs and outputs")
+        for op, y, a in zip(ops, ys, Ays):
+            if y.shape != a.shape or tuple(y.shape[1:]) != (4, op.n) or not (y.is_contiguous() and a.is_contiguous()):
+                raise ValueError(f"y and Ay must be contiguous [nrhs, 4, {op.n}] tensors")
+        k = len(ops)
+        self._keep = (list(ys), list(Ays))
+        h = C.c_void_p()
+        arr_ops = (C.c_void_p * k)(*[op.handle for op in ops])
+        arr_y = (C.c_void_p * k)(*[y.data_ptr() for y in ys])
+        arr_a = (C.c_void_p * k)(*[a.data_ptr() for a in Ays])
+        arr_n = (C.c_int * k)(*[int(y.shape[0]) for y in ys])
+        _check(lib().nmuller_graph_capture(C.byref(h), k, arr_ops, arr_y, arr_n, arr_a), "nmuller_graph_capture")
+        self.handle = h.value
+        n = C.c_int64()
+        _check(lib().ifgf_graph_nodes(self.handle, C.byref(n)), "ifgf_graph_nodes")
+        self.nodes = n.value
+
+    def launch(self, stream=None):
+        _check(lib().ifgf_graph_launch(self.handle, _stream_ptr(stream)), "ifgf_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().ifgf_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 MLP_BF16 = 0

@@ -1,6 +1,7 @@
 // C-ABI of libifgf: plan construction, upload and the IFGF apply driver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -90,7 +91,9 @@ struct ifgf_plan_s {
   // matrix-core path (Pa = 5): K-slot cone layout, FP32 or FP64 cone data
   bool mfma = false;
   bool fp32 = false;
-  void* d_af = nullptr;                 // FP32 weighted densities [n][16]
+  void* d_af = nullptr;                 // weighted densities of a batch [n][R][16]
+  int rcap = 1;                         // right-hand sides per pass the buffers hold
+  int rsel = 1;                         // right-hand sides per pass in use (<= rcap)
   std::vector<PropGroups> groups;       // groups[d]: propagation into level d
 };
 
@@ -99,6 +102,7 @@ hipEvent_t timer_begin(ifgf_plan_s* p, hipStream_t st) { return p ? p->timer.beg
 void timer_end(ifgf_plan_s* p, const char* name, hipEvent_t ev, hipStream_t st, double units) {
   if (p) p->timer.end(name, ev, st, units);
 }
+bool timing_on(ifgf_plan_s* p) { return p && p->timer.on; }
 }  // namespace ifgf
 
 namespace {
@@ -187,6 +191,7 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->precision = IFGF_FP64;
   opt->max_nrhs = 1;
   opt->host_only = 0;
+  opt->batch_columns = 1;
 }
 
 int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* normals,
@@ -204,6 +209,9 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   if (opt.na_init <= 0) opt.na_init = 2;
   if (opt.leaf_wavelengths <= 0.0) opt.leaf_wavelengths = 0.25;
   if (opt.max_nrhs <= 0) opt.max_nrhs = 1;
+  if (opt.batch_columns <= 0) opt.batch_columns = 1;
+  if (opt.batch_columns != 1 && opt.batch_columns != 2 && opt.batch_columns != 4)
+    return set_error(IFGF_EINVAL, "batch_columns must be 1, 2 or 4");
   if (opt.Ps <= 0 || opt.Pa <= 0) tol_to_orders(tol, &opt.Ps, &opt.Pa);
   if (opt.Ps > kMaxP || opt.Pa > kMaxP || opt.Ps < 1 || opt.Pa < 1)
     return set_error(IFGF_EINVAL, "Ps and Pa must lie in [1, 8]");
@@ -328,8 +336,12 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     std::vector<int32_t>().swap(L.tp_slot);
     std::vector<int32_t>().swap(L.pp_slot);
   }
+  // right-hand sides stacked into the cone-data columns (matrix-core path)
+  p->rcap = p->mfma ? std::min(std::min(opt.max_nrhs, opt.batch_columns), p->fp32 ? 4 : 2) : 1;
+  if (p->rcap == 3) p->rcap = 2;
+  p->rsel = p->rcap;
   p->d_a = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kNS));
-  p->d_out_s = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kOut));
+  p->d_out_s = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kOut * p->rcap));
   if (!p->d_a || !p->d_out_s) {
     delete p;
     return set_error(IFGF_ENOMEM, "device workspace allocation failed");
@@ -337,14 +349,14 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   // A matrix-core plan can run in either precision (ifgf_set_precision), so
   // its FP32 density copy and FP64-sized cone buffers always exist.
   if (p->mfma) {
-    p->d_af = ar.alloc(sizeof(float) * 16 * (size_t)n);
+    p->d_af = ar.alloc(sizeof(double) * 16 * (size_t)n * p->rcap);
     if (!p->d_af) {
       delete p;
       return set_error(IFGF_ENOMEM, "device workspace allocation failed");
     }
   }
   if (p->max_slots > 0) {
-    size_t vb = p->mfma ? sizeof(double) * (size_t)p->max_slots * kslot_rows(opt.Ps) * 32
+    size_t vb = p->mfma ? sizeof(double) * (size_t)p->max_slots * kslot_rows(opt.Ps) * 32 * p->rcap
                         : sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
     p->d_vals[0] = static_cast<double2*>(ar.alloc(vb));
     p->d_vals[1] = static_cast<double2*>(ar.alloc(vb));
@@ -369,6 +381,60 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
   const int64_t n = H.n;
   const double k0 = H.k[0], k1 = H.k[1];
   PhaseTimer& T = p->timer;
+  if (p->mfma && H.D >= 3) {
+    // matrix-core path: R right-hand sides per pass share the geometry
+    const int rmax = std::min(p->rsel, max_batch_columns(p->fp32));
+    for (int r0 = 0; r0 < nrhs;) {
+      const int rem = nrhs - r0;
+      const int R = (rem >= 4 && rmax >= 4) ? 4 : ((rem >= 2 && rmax >= 2) ? 2 : 1);
+      const double2* dens = static_cast<const double2*>(densities) + (int64_t)r0 * kNS * n;
+      hipError_t e;
+      for (int r = 0; r < R; ++r) {
+        hipEvent_t ev = T.begin(st);
+        if ((e = launch_gather_weighted(dens + (int64_t)r * kNS * n, p->d_perm, p->d_w, n, p->d_a, st)) !=
+            hipSuccess)
+          return set_hip_error(e, "gather");
+        T.end("gather", ev, st, (double)n);
+        ev = T.begin(st);
+        if ((e = launch_near(p->lev[H.D], p->d_leaf_of_point, p->d_xs, p->d_nrm, p->d_a, n, k0, k1,
+                             p->d_out_s + (int64_t)r * kOut * n, st)) != hipSuccess)
+          return set_hip_error(e, "near");
+        T.end("near", ev, st, (double)H.near_pairs);
+      }
+      if ((e = mf_gather(p->fp32, R, dens, p->d_perm, p->d_w, n, p->d_af, st)) != hipSuccess)
+        return set_hip_error(e, "gather batch");
+      int cur = 0;
+      hipEvent_t ev = T.begin(st);
+      if ((e = mf_leaf(p->fp32, H.Ps, R, p->lev[H.D], p->ic, p->d_xs, p->d_af, k0, k1, p->d_vals[cur], st)) !=
+          hipSuccess)
+        return set_hip_error(e, "leaf");
+      T.end("leaf", ev, st, (double)H.leaf_pairs * R);
+      for (int d = H.D; d >= 3; --d) {
+        ev = T.begin(st);
+        if ((e = mf_targets(p->fp32, H.Ps, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1, p->d_vals[cur],
+                            p->d_out_s, st)) != hipSuccess)
+          return set_hip_error(e, "targets");
+        T.end("targets", ev, st, (double)H.lev[d].tp_off.back() * R);
+        if (d > 3) {
+          ev = T.begin(st);
+          if ((e = mf_propagate(p->fp32, H.Ps, R, p->lev[d], p->lev[d - 1], p->ic, p->groups[d - 1], k0, k1,
+                                p->d_vals[cur], p->d_vals[cur ^ 1], st)) != hipSuccess)
+            return set_hip_error(e, "propagate");
+          T.end("propagate", ev, st, (double)H.lev[d - 1].pp_off.back() * R);
+          cur ^= 1;
+        }
+      }
+      for (int r = 0; r < R; ++r) {
+        ev = T.begin(st);
+        double2* o = static_cast<double2*>(out) + (int64_t)(r0 + r) * kOut * n;
+        if ((e = launch_scatter_out(p->d_out_s + (int64_t)r * kOut * n, p->d_perm, n, o, st)) != hipSuccess)
+          return set_hip_error(e, "scatter");
+        T.end("scatter", ev, st, (double)n);
+      }
+      r0 += R;
+    }
+    return IFGF_OK;
+  }
   for (int r = 0; r < nrhs; ++r) {
     const double2* dens = static_cast<const double2*>(densities) + (int64_t)r * kNS * n;
     double2* o = static_cast<double2*>(out) + (int64_t)r * kOut * n;
@@ -382,35 +448,7 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
                          p->d_out_s, st)) != hipSuccess)
       return set_hip_error(e, "near");
     T.end("near", ev, st, (double)H.near_pairs);
-    if (H.D >= 3 && p->mfma) {
-      int cur = 0;
-      const void* av = p->d_a;
-      if (p->fp32) {
-        if ((e = mf_gather(true, dens, p->d_perm, p->d_w, n, p->d_af, st)) != hipSuccess)
-          return set_hip_error(e, "gather fp32");
-        av = p->d_af;
-      }
-      ev = T.begin(st);
-      if ((e = mf_leaf(p->fp32, H.Ps, p->lev[H.D], p->ic, p->d_xs, av, k0, k1, p->d_vals[cur], st)) !=
-          hipSuccess)
-        return set_hip_error(e, "leaf");
-      T.end("leaf", ev, st, (double)H.leaf_pairs);
-      for (int d = H.D; d >= 3; --d) {
-        ev = T.begin(st);
-        if ((e = mf_targets(p->fp32, H.Ps, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1, p->d_vals[cur],
-                            p->d_out_s, st)) != hipSuccess)
-          return set_hip_error(e, "targets");
-        T.end("targets", ev, st, (double)H.lev[d].tp_off.back());
-        if (d > 3) {
-          ev = T.begin(st);
-          if ((e = mf_propagate(p->fp32, H.Ps, p->lev[d], p->lev[d - 1], p->ic, p->groups[d - 1], k0, k1,
-                                p->d_vals[cur], p->d_vals[cur ^ 1], st)) != hipSuccess)
-            return set_hip_error(e, "propagate");
-          T.end("propagate", ev, st, (double)H.lev[d - 1].pp_off.back());
-          cur ^= 1;
-        }
-      }
-    } else if (H.D >= 3) {
+    if (H.D >= 3) {
       int cur = 0;
       ev = T.begin(st);
       if ((e = launch_leaf(p->lev[H.D], p->ic, p->d_xs, p->d_a, k0, k1, p->d_vals[cur], st)) !=
@@ -521,6 +559,56 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
   s += "}}";
   if (s.size() + 1 > cap) return set_error(IFGF_EINVAL, "json buffer too small");
   std::memcpy(json, s.c_str(), s.size() + 1);
+  return IFGF_OK;
+}
+
+int ifgf_autotune(ifgf_plan_t p, void* stream, int* chosen) {
+  clear_error();
+  if (!p) return set_error(IFGF_EINVAL, "plan is NULL");
+  if (p->opt.host_only) return set_error(IFGF_ENOTPLANNED, "plan was built with host_only");
+  if (p->timer.on) return set_error(IFGF_EINVAL, "switch per-kernel timing off before tuning");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t n = p->host.n;
+  const int top = std::min(p->rcap, max_batch_columns(p->fp32));
+  int best = 1;
+  if (p->mfma && top > 1) {
+    DeviceArena tmp;
+    void* dens = tmp.alloc(sizeof(double2) * kNS * (size_t)n * top);
+    void* out = tmp.alloc(sizeof(double2) * kOut * (size_t)n * top);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (!dens || !out) return set_error(IFGF_ENOMEM, "autotune buffers");
+    hipError_t e;
+    if ((e = hipMemsetAsync(dens, 0, sizeof(double2) * kNS * (size_t)n * top, st)) != hipSuccess ||
+        (e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess)
+      return set_hip_error(e, "autotune setup");
+    double best_ms = 1e300;
+    const int saved = p->rsel;
+    for (int R = 1; R <= top; R *= 2) {
+      p->rsel = R;
+      int rc = ifgf_apply(p, dens, R, out, stream);   // warm-up
+      if (!rc) {
+        (void)hipEventRecord(a, st);
+        rc = ifgf_apply(p, dens, R, out, stream);
+        (void)hipEventRecord(b, st);
+      }
+      float ms = 0.f;
+      if (rc || (e = hipEventSynchronize(b)) != hipSuccess || (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) {
+        p->rsel = saved;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return rc ? rc : set_hip_error(e, "autotune timing");
+      }
+      const double per = ms / R;
+      if (per < best_ms) {
+        best_ms = per;
+        best = R;
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  p->rsel = best;
+  if (chosen) *chosen = best;
   return IFGF_OK;
 }
 

@@ -64,4 +64,5 @@ struct ifgf_plan_s;
 namespace ifgf {
 hipEvent_t timer_begin(ifgf_plan_s* p, hipStream_t st);
 void timer_end(ifgf_plan_s* p, const char* name, hipEvent_t ev, hipStream_t st, double units);
+bool timing_on(ifgf_plan_s* p);   // per-kernel timing switched on
 }  // namespace ifgf

@@ -10,9 +10,9 @@
 // KS = nab + ceil(nab / 4), nab = 5 Ps:
 //   c < 4 : row 4 * ab + c           (ab = 5 a + b)
 //   c = 4 : row 4 * nab + ab
-// remaining rows are zero padding.  A row holds 32 reals: the real parts of
-// the 16 complex columns (column = 8 * kernel + density) then their imaginary
-// parts.  With this order the MFMA lane group g = lane / 16 always supplies
+// remaining rows are zero padding.  A row holds R groups of 32 reals, one
+// group per right-hand side of the batch: the real parts of the 16 complex
+// columns (column = 8 * kernel + density) then their imaginary parts.  With this order the MFMA lane group g = lane / 16 always supplies
 // the phi-node c = g (first nab k-steps) so the interpolation weight of a
 // lane is one product of per-point Lagrange factors.
 //
@@ -21,6 +21,8 @@
 // evaluated in cone-centred coordinates so that FP32 keeps relative accuracy:
 // phases use r_child - r_parent = (|d|^2 - 2 Y.d) / (r_child + r_parent).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "device.hpp"
 #include "ifgf_mfma.hpp"
@@ -172,29 +174,32 @@ __device__ __forceinline__ int row_of_point(int p, int nab) {
 }
 
 // ---------------------------------------------------------------------------
-// weighted densities in sorted order: a[i][m] = w_i phi_m(perm[i])
+// weighted densities in sorted order: a[i][r][m] = w_i phi_{r,m}(perm[i]) for
+// the R right-hand sides dens[r][m][.]
 template <class T>
 __global__ void k_gather(const double2* __restrict__ dens, const int64_t* __restrict__ perm,
-                         const double* __restrict__ w, int64_t n, T* __restrict__ a) {
+                         const double* __restrict__ w, int64_t n, int R, T* __restrict__ a) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * 8) return;
-  int64_t i = t / 8;
+  if (t >= n * 8 * R) return;
+  int64_t i = t / (8 * R);
+  int r = (int)((t / 8) % R);
   int m = (int)(t % 8);
-  double2 v = dens[(int64_t)m * n + perm[i]];
+  double2 v = dens[((int64_t)r * 8 + m) * n + perm[i]];
   a[2 * t] = (T)(v.x * w[i]);
   a[2 * t + 1] = (T)(v.y * w[i]);
 }
 
-// leaf cone values: thread per (slot, row)
-template <int PS, class T>
+// leaf cone values: thread per (slot, row, right-hand side)
+template <int PS, class T, int R>
 __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const double* __restrict__ xs, const T* __restrict__ a,
                          double k0, double k1, T* __restrict__ V) {
   constexpr int NAB = PS * 5;
   constexpr int K = 4 * (NAB + (NAB + 3) / 4);
   int64_t t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (t >= L.nslots * K) return;
-  int64_t q = t / K;
-  int row = (int)(t % K);
+  if (t >= L.nslots * K * R) return;
+  int64_t q = t / (K * R);
+  int row = (int)((t / R) % K);
+  const int r = (int)(t % R);
   T* o = V + t * 32;
   int p = point_of_row(row, NAB);
   if (p < 0) {
@@ -218,7 +223,7 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
     const T rxy = tsqrt<T>(dx * dx + dy * dy + dz * dz);
     const T diff = (yx * yx + yy * yy + yz * yz - (T)2 * (Yx * yx + Yy * yy + Yz * yz)) / (rxy + rxc);
     const T ratio = rxc / rxy;
-    const T* aj = a + (int64_t)j * 16;
+    const T* aj = a + ((int64_t)j * R + r) * 16;
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) {
       T sn, cs;
@@ -242,7 +247,7 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
 // wavefronts.  A wavefront takes its tiles four at a time: one lane per point
 // evaluates the child-cone coordinates, Lagrange factors and re-centring
 // factor of its point into wave-private LDS, then the four MFMA tiles run.
-template <int PS, class T>
+template <int PS, class T, int R>
 __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, InterpC ic, PropGroups G,
                                                    double k0, double k1, const T* __restrict__ Vc,
                                                    T* __restrict__ Vp) {
@@ -251,14 +256,15 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   constexpr int K = 4 * KS;
   constexpr int NPTS = NAB * 5;
   constexpr int GW = 20;                // Ls [0, PS), Lt [6, 11), Lp [11, 16), factor [16, 20)
-  __shared__ T acc[NPTS][33];
+  constexpr int W = 32 * R;             // reals per cone row
+  __shared__ T acc[NPTS][W + 1];
   __shared__ T gbuf[4][64][GW];         // per wavefront: 4 tiles x 16 rows
   __shared__ T geo[NPTS][4];            // parent points about the parent centre, and r_p
   const int64_t q = xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, gl = lane >> 4;
-  for (int i = tid; i < NPTS * 33; i += 256) (&acc[0][0])[i] = (T)0;
+  for (int i = tid; i < NPTS * (W + 1); i += 256) (&acc[0][0])[i] = (T)0;
   const int32_t pb = P.slot_box[q];
   const int pcone = P.slot_cone[q];
   const double* cp = P.centers + 3 * pb;
@@ -350,7 +356,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       const int cnt = G.count[gg];
       const int tt = bt[b];
       const int64_t pstart = G.start[gg] + tt;
-      const T* Vs = Vc + (int64_t)G.slot[gg] * K * 32 + gl * 32;
+      const T* Vs = Vc + (int64_t)G.slot[gg] * K * W + gl * W;
       const T* me = gb[16 * b + r16];
       T Ls[PS], Lt[5];
 #pragma unroll
@@ -362,7 +368,12 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       T st[NAB];
 #pragma unroll
       for (int ab = 0; ab < NAB; ++ab) st[ab] = Ls[ab / 5] * Lt[ab % 5];
-      typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+      typename MF<T>::acc c0[R], c1[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        c0[r] = typename MF<T>::acc{0, 0, 0, 0};
+        c1[r] = typename MF<T>::acc{0, 0, 0, 0};
+      }
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
         T av;
@@ -377,9 +388,12 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
           sel = (gl == 3) ? ((m0 + 3 < NAB) ? st[m0 + 3 < NAB ? m0 + 3 : 0] : (T)0) : sel;
           av = sel * lp4;
         }
-        const T* vrow = Vs + (int64_t)(4 * j) * 32;
-        c0 = MF<T>::mma(av, vrow[r16], c0);
-        c1 = MF<T>::mma(av, vrow[16 + r16], c1);
+        const T* vrow = Vs + (int64_t)(4 * j) * W;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          c0[r] = MF<T>::mma(av, vrow[32 * r + r16], c0[r]);
+          c1[r] = MF<T>::mma(av, vrow[32 * r + 16 + r16], c1[r]);
+        }
       }
       // lane holds rows MF::row(lane, e), complex column r16 (kernel r16 / 8)
       const int qq = r16 >> 3;
@@ -389,18 +403,21 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         if (tt + orow < cnt) {
           const int po = (int)G.pts[pstart + orow];
           const T fr = gb[16 * b + orow][16 + 2 * qq], fi = gb[16 * b + orow][17 + 2 * qq];
-          const T vr = c0[e], vi = c1[e];
-          atomicAdd(&acc[po][r16], fr * vr - fi * vi);
-          atomicAdd(&acc[po][16 + r16], fr * vi + fi * vr);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const T vr = c0[r][e], vi = c1[r][e];
+            atomicAdd(&acc[po][32 * r + r16], fr * vr - fi * vi);
+            atomicAdd(&acc[po][32 * r + 16 + r16], fr * vi + fi * vr);
+          }
         }
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  T* out = Vp + q * (int64_t)K * 32;
-  for (int i = tid; i < K * 32; i += 256) {
-    const int row = i >> 5, col = i & 31;
+  T* out = Vp + q * (int64_t)K * W;
+  for (int i = tid; i < K * W; i += 256) {
+    const int row = i / W, col = i % W;
     const int p = point_of_row(row, NAB);
     out[i] = p >= 0 ? acc[p][col] : (T)0;
   }
@@ -408,7 +425,8 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 
 // ---------------------------------------------------------------------------
 // interpolation onto cousin targets: thread per target, loop over its cousins
-template <int PS, class T>
+// blockIdx.y selects the right-hand side r of the batch of R
+template <int PS, class T, int R>
 __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const double* __restrict__ xs,
                             const double* __restrict__ nrm, int64_t n, double k0, double k1,
                             const T* __restrict__ V, double2* __restrict__ out_s) {
@@ -421,7 +439,8 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
   if (e0 == e1) return;
   const T nx = (T)nrm[3 * i], ny = (T)nrm[3 * i + 1], nz = (T)nrm[3 * i + 2];
   const T kk[2] = {(T)k0, (T)k1};
-  double2* o = out_s + i * 28;
+  const int rr = blockIdx.y;
+  double2* o = out_s + ((int64_t)rr * n + i) * 28;
   T Sr[2][8], Si[2][8], Dr[2][6], Di[2][6];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -464,7 +483,7 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
     for (int m = 0; m < 32; ++m) F[m] = (T)0;
 #pragma unroll
     for (int m = 0; m < 24; ++m) FD[m] = (T)0;
-    const T* Vs = V + (int64_t)slot * K * 32;
+    const T* Vs = V + (int64_t)slot * K * 32 * R + 32 * rr;
     // radial index a runs in a rolled loop; Ls/dLs rotate so indices stay static
 #pragma unroll 1
     for (int a = 0; a < PS; ++a) {
@@ -496,7 +515,7 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
             Lp[4] = l0;
             dLp[4] = d0;
           }
-          const T* vr = Vs + (int64_t)row * 32;
+          const T* vr = Vs + (int64_t)row * 32 * R;
 #pragma unroll
           for (int m = 0; m < 32; ++m) F[m] += w * vr[m];
 #pragma unroll
@@ -548,66 +567,106 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
 
 inline unsigned nblk(int64_t w, int bs) { return (unsigned)((w + bs - 1) / bs); }
 
-template <int PS, class T>
+template <int PS, class T, int R>
 hipError_t leaf_t(const DevLevel& L, const InterpC& ic, const double* xs, const void* a, double k0,
                   double k1, void* V, hipStream_t st) {
   constexpr int NAB = PS * 5;
   constexpr int K = 4 * (NAB + (NAB + 3) / 4);
-  int64_t work = L.nslots * K;
+  int64_t work = L.nslots * K * R;
   if (work <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_leaf_k<PS, T>), dim3(nblk(work, 256)), dim3(256), 0, st, L, ic, xs,
+  hipLaunchKernelGGL((k_leaf_k<PS, T, R>), dim3(nblk(work, 256)), dim3(256), 0, st, L, ic, xs,
                      static_cast<const T*>(a), k0, k1, static_cast<T*>(V));
   return hipGetLastError();
 }
-template <int PS, class T>
+template <int PS, class T, int R>
 hipError_t prop_t(const DevLevel& C, const DevLevel& P, const InterpC& ic, const PropGroups& G,
                   double k0, double k1, const void* Vc, void* Vp, hipStream_t st) {
   if (P.nslots <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_prop_mfma<PS, T>), dim3((unsigned)P.nslots), dim3(256), 0, st, C, P, ic, G, k0, k1,
+  hipLaunchKernelGGL((k_prop_mfma<PS, T, R>), dim3((unsigned)P.nslots), dim3(256), 0, st, C, P, ic, G, k0, k1,
                      static_cast<const T*>(Vc), static_cast<T*>(Vp));
   return hipGetLastError();
 }
-template <int PS, class T>
+template <int PS, class T, int R>
 hipError_t targets_t(const DevLevel& L, const InterpC& ic, const double* xs, const double* nrm,
                      int64_t n, double k0, double k1, const void* V, double2* out_s, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_targets_k<PS, T>), dim3(nblk(n, 64)), dim3(64), 0, st, L, ic, xs, nrm, n, k0, k1,
+  hipLaunchKernelGGL((k_targets_k<PS, T, R>), dim3(nblk(n, 64), R), dim3(64), 0, st, L, ic, xs, nrm, n, k0, k1,
                      static_cast<const T*>(V), out_s);
   return hipGetLastError();
 }
 
+// R = 1, 2 or 4 right-hand sides per pass; FP64 takes at most 2 (the LDS of
+// the propagation at R = 4 would exceed a workgroup's 160 KB)
+template <int PS, class T>
+hipError_t leaf_r(int R, const DevLevel& L, const InterpC& ic, const double* xs, const void* a, double k0,
+                  double k1, void* V, hipStream_t st) {
+  switch (R) {
+    case 1: return leaf_t<PS, T, 1>(L, ic, xs, a, k0, k1, V, st);
+    case 2: return leaf_t<PS, T, 2>(L, ic, xs, a, k0, k1, V, st);
+    case 4:
+      if constexpr (std::is_same<T, float>::value) return leaf_t<PS, T, 4>(L, ic, xs, a, k0, k1, V, st);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+template <int PS, class T>
+hipError_t prop_r(int R, const DevLevel& C, const DevLevel& P, const InterpC& ic, const PropGroups& G,
+                  double k0, double k1, const void* Vc, void* Vp, hipStream_t st) {
+  switch (R) {
+    case 1: return prop_t<PS, T, 1>(C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 2: return prop_t<PS, T, 2>(C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 4:
+      if constexpr (std::is_same<T, float>::value) return prop_t<PS, T, 4>(C, P, ic, G, k0, k1, Vc, Vp, st);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+template <int PS, class T>
+hipError_t targets_r(int R, const DevLevel& L, const InterpC& ic, const double* xs, const double* nrm,
+                     int64_t n, double k0, double k1, const void* V, double2* out_s, hipStream_t st) {
+  switch (R) {
+    case 1: return targets_t<PS, T, 1>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 2: return targets_t<PS, T, 2>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 4:
+      if constexpr (std::is_same<T, float>::value)
+        return targets_t<PS, T, 4>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
 template <class T>
-hipError_t dispatch_leaf(int Ps, const DevLevel& L, const InterpC& ic, const double* xs, const void* a,
+hipError_t dispatch_leaf(int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs, const void* a,
                          double k0, double k1, void* V, hipStream_t st) {
   switch (Ps) {
-    case 3: return leaf_t<3, T>(L, ic, xs, a, k0, k1, V, st);
-    case 4: return leaf_t<4, T>(L, ic, xs, a, k0, k1, V, st);
-    case 5: return leaf_t<5, T>(L, ic, xs, a, k0, k1, V, st);
-    case 6: return leaf_t<6, T>(L, ic, xs, a, k0, k1, V, st);
+    case 3: return leaf_r<3, T>(R, L, ic, xs, a, k0, k1, V, st);
+    case 4: return leaf_r<4, T>(R, L, ic, xs, a, k0, k1, V, st);
+    case 5: return leaf_r<5, T>(R, L, ic, xs, a, k0, k1, V, st);
+    case 6: return leaf_r<6, T>(R, L, ic, xs, a, k0, k1, V, st);
   }
   return hipErrorInvalidValue;
 }
 template <class T>
-hipError_t dispatch_prop(int Ps, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+hipError_t dispatch_prop(int Ps, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
                          const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
                          hipStream_t st) {
   switch (Ps) {
-    case 3: return prop_t<3, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 4: return prop_t<4, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 5: return prop_t<5, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 6: return prop_t<6, T>(C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 3: return prop_r<3, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 4: return prop_r<4, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 5: return prop_r<5, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
+    case 6: return prop_r<6, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
   }
   return hipErrorInvalidValue;
 }
 template <class T>
-hipError_t dispatch_targets(int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t dispatch_targets(int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                             const double* nrm, int64_t n, double k0, double k1, const void* V,
                             double2* out_s, hipStream_t st) {
   switch (Ps) {
-    case 3: return targets_t<3, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 4: return targets_t<4, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 5: return targets_t<5, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 6: return targets_t<6, T>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 3: return targets_r<3, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 4: return targets_r<4, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 5: return targets_r<5, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    case 6: return targets_r<6, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
   }
   return hipErrorInvalidValue;
 }
@@ -621,36 +680,38 @@ int kslot_rows(int Ps) {
   return 4 * (nab + (nab + 3) / 4);
 }
 
-hipError_t mf_gather(bool fp32, const double2* dens, const int64_t* perm, const double* w, int64_t n,
+int max_batch_columns(bool fp32) { return fp32 ? 4 : 2; }
+
+hipError_t mf_gather(bool fp32, int R, const double2* dens, const int64_t* perm, const double* w, int64_t n,
                      void* a, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_gather<float>, dim3(nblk(n * 8, 256)), dim3(256), 0, st, dens, perm, w, n,
+    hipLaunchKernelGGL(k_gather<float>, dim3(nblk(n * 8 * R, 256)), dim3(256), 0, st, dens, perm, w, n, R,
                        static_cast<float*>(a));
   else
-    hipLaunchKernelGGL(k_gather<double>, dim3(nblk(n * 8, 256)), dim3(256), 0, st, dens, perm, w, n,
+    hipLaunchKernelGGL(k_gather<double>, dim3(nblk(n * 8 * R, 256)), dim3(256), 0, st, dens, perm, w, n, R,
                        static_cast<double*>(a));
   return hipGetLastError();
 }
 
-hipError_t mf_leaf(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t mf_leaf(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                    const void* a, double k0, double k1, void* V, hipStream_t st) {
-  return fp32 ? dispatch_leaf<float>(Ps, L, ic, xs, a, k0, k1, V, st)
-              : dispatch_leaf<double>(Ps, L, ic, xs, a, k0, k1, V, st);
+  return fp32 ? dispatch_leaf<float>(Ps, R, L, ic, xs, a, k0, k1, V, st)
+              : dispatch_leaf<double>(Ps, R, L, ic, xs, a, k0, k1, V, st);
 }
 
-hipError_t mf_propagate(bool fp32, int Ps, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+hipError_t mf_propagate(bool fp32, int Ps, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
                         const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
                         hipStream_t st) {
-  return fp32 ? dispatch_prop<float>(Ps, C, P, ic, G, k0, k1, Vc, Vp, st)
-              : dispatch_prop<double>(Ps, C, P, ic, G, k0, k1, Vc, Vp, st);
+  return fp32 ? dispatch_prop<float>(Ps, R, C, P, ic, G, k0, k1, Vc, Vp, st)
+              : dispatch_prop<double>(Ps, R, C, P, ic, G, k0, k1, Vc, Vp, st);
 }
 
-hipError_t mf_targets(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t mf_targets(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                       const double* nrm, int64_t n, double k0, double k1, const void* V,
                       double2* out_s, hipStream_t st) {
-  return fp32 ? dispatch_targets<float>(Ps, L, ic, xs, nrm, n, k0, k1, V, out_s, st)
-              : dispatch_targets<double>(Ps, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+  return fp32 ? dispatch_targets<float>(Ps, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st)
+              : dispatch_targets<double>(Ps, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
 }
 
 }  // namespace ifgf

@@ -27,15 +27,20 @@ struct PropGroups {
 
 bool mfma_path_supported(int Ps, int Pa);
 int kslot_rows(int Ps);   // rows per cone in K-slot order
+// Right-hand sides per pass: cone rows hold R groups of 32 reals, R in {1, 2, 4}
+// (FP32) or {1, 2} (FP64).
+int max_batch_columns(bool fp32);
 
-hipError_t mf_gather(bool fp32, const double2* dens, const int64_t* perm, const double* w, int64_t n,
+// a: [n][R][16] weighted densities of dens[r][8][n], r < R
+hipError_t mf_gather(bool fp32, int R, const double2* dens, const int64_t* perm, const double* w, int64_t n,
                      void* a, hipStream_t st);
-hipError_t mf_leaf(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t mf_leaf(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                    const void* a, double k0, double k1, void* V, hipStream_t st);
-hipError_t mf_propagate(bool fp32, int Ps, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+hipError_t mf_propagate(bool fp32, int Ps, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
                         const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
                         hipStream_t st);
-hipError_t mf_targets(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const double* xs,
+// out_s: [R][n][28], accumulated
+hipError_t mf_targets(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                       const double* nrm, int64_t n, double k0, double k1, const void* V,
                       double2* out_s, hipStream_t st);
 

@@ -1,0 +1,126 @@
+"""Batching: many right-hand sides and many bodies through one graph launch.
+
+Bars: batched applies equal looped single-RHS applies, and every graph
+replay equals the eager result, to 1e-12 relative (the propagation's LDS
+accumulation order is not fixed between runs; nothing else differs).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rel(a, b):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def test_64_rhs_batched_equals_looped_and_graph_replays():
+    from paper_2408_02274_amd import NMullerGraph, NMullerOperator
+    s = synth.cube_sphere(2, 8, 1.0)
+    _say("[gpu] batch: config-1 sphere, 64 RHS")
+    op = NMullerOperator(s, 1.0, 2.25, tol=1e-3, Ps=5, Pa=5, max_nrhs=64)
+    y = torch.from_numpy(synth.complex_normal((64, 4, s.n), 3)).to("cuda")
+    ref = op.apply(y)
+    for r in (0, 17, 63):
+        one = op.apply(y[r:r + 1].contiguous())
+        assert _rel(one[0], ref[r]) < 1e-12
+    out = torch.zeros_like(y)
+    g = NMullerGraph([op], [y], [out])
+    assert g.nodes >= 64
+    other = torch.from_numpy(synth.complex_normal((1, 4, s.n), 4)).to("cuda")
+    for rep in range(3):
+        out.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        assert _rel(out, ref) < 1e-12, f"replay {rep}"
+        op.apply(other)                      # eager work between replays
+        torch.cuda.synchronize()
+    # new contents of the captured input are picked up by the next replay
+    y.copy_(torch.from_numpy(synth.complex_normal((64, 4, s.n), 5)).to("cuda"))
+    ref2 = op.apply(y)
+    g.launch()
+    torch.cuda.synchronize()
+    assert _rel(out, ref2) < 1e-12
+    g.close()
+    op.close()
+
+
+def test_uneven_bodies_in_one_graph_fp32():
+    from paper_2408_02274_amd import NMullerGraph, NMullerOperator
+    from paper_2408_02274_amd import binding as B
+    specs = [(0.6, 0.8, 0.7, 1.5, 2), (1.1, 0.7, 0.9, 3.0, 2), (0.9, 1.3, 1.0, 2.2, 3)]
+    ops, ys, outs, refs = [], [], [], []
+    for i, (a, b, c, eps, npf) in enumerate(specs):
+        s = synth.ellipsoid(a, b, c, npf, 8)
+        _say(f"[gpu] batch body {i}: n = {s.n}")
+        op = NMullerOperator(s, 1.0, eps, tol=1e-3, Ps=5, Pa=5, precision=B.IFGF_FP32, max_nrhs=2)
+        y = torch.from_numpy(synth.complex_normal((2, 4, s.n), 10 + i)).to("cuda")
+        ops.append(op)
+        ys.append(y)
+        outs.append(torch.zeros_like(y))
+        refs.append(op.apply(y))
+    g = NMullerGraph(ops, ys, outs)
+    for rep in range(2):
+        g.launch()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert _rel(o, r) < 1e-6   # FP32 form: accumulation order inside FP32 sums
+        for o in outs:
+            o.zero_()
+    g.close()
+    # timing on: capture is refused
+    B.ifgf_set_timing(ops[0].ifgf_handle(), True)
+    with pytest.raises(B.IFGFError):
+        NMullerGraph(ops[:1], ys[:1], outs[:1])
+    B.ifgf_set_timing(ops[0].ifgf_handle(), False)
+    for op in ops:
+        op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_column_batches_equal_single_rhs(prec):
+    """7 right-hand sides run as column batches (FP32: 4 + 2 + 1, FP64:
+    2 + 2 + 2 + 1) equal seven single-RHS applies."""
+    from paper_2408_02274_amd import IFGFPlan
+    from paper_2408_02274_amd import binding as B
+    s = synth.ellipsoid(1.1, 0.8, 0.9, 2, 8)
+    w = np.random.default_rng(4).uniform(0.5, 1.5, s.n)
+    ks = (3 * math.pi, 2 * math.pi)
+    p = B.IFGF_FP32 if prec == "fp32" else B.IFGF_FP64
+    _say(f"[gpu] column batches {prec}, n = {s.n}")
+    batched = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-3, Ps=5, Pa=5, precision=p, max_nrhs=7)
+    single = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-3, Ps=5, Pa=5, precision=p)
+    d = torch.from_numpy(synth.complex_normal((7, 8, s.n), 8)).to("cuda")
+    out = batched.apply(d)
+    bar = 1e-6 if prec == "fp32" else 1e-12
+    for r in range(7):
+        ref = single.apply(d[r:r + 1].contiguous())[0]
+        assert _rel(out[r], ref) < bar, f"rhs {r}"
+    batched.close()
+    single.close()
+
+
+def test_autotune_picks_a_valid_column_batch():
+    from paper_2408_02274_amd import IFGFPlan
+    from paper_2408_02274_amd import binding as B
+    s = synth.cube_sphere(2, 8, 1.0)
+    w = np.full(s.n, 4 * math.pi / s.n)
+    p = IFGFPlan(s.x, s.normal, w, 3 * math.pi, 2 * math.pi, 1e-3, Ps=5, Pa=5, precision=B.IFGF_FP32,
+                 max_nrhs=8, batch_columns=4)
+    _say("[gpu] autotune")
+    r = B.ifgf_autotune(p.handle)
+    assert r in (1, 2, 4)
+    d = torch.from_numpy(synth.complex_normal((8, 8, s.n), 9)).to("cuda")
+    out = p.apply(d)
+    one = p.apply(d[5:6].contiguous())
+    assert _rel(out[5], one[0]) < 1e-6
+    p.close()
