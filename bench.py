@@ -15,9 +15,10 @@ cone grids and interpolation in FP32, corrections, assembly and GMRES in
 FP64.  The plain FP64 form of the same operator is timed beside it.
 
 After the timed steps, GMRES solves of a plane-wave right-hand side (+z,
-polarised x) to a 1e-4 true FP64 residual: mixed, FP64, flexible GMRES with
-the identity-part scaling D^-1, and flexible GMRES with the learned
-preconditioner (trained parameters from paper_2408_02274_amd/weights).
+polarised x) to a 1e-4 true FP64 residual: mixed, FP64, and flexible GMRES
+with the identity-part scaling D^-1.  The learned preconditioner (trained
+parameters from paper_2408_02274_amd/weights) is timed on a held-out body of
+the ellipsoid family it was trained on, against plain GMRES there.
 
 Prints one JSON line.
 """
@@ -143,6 +144,34 @@ def batching(log, reps=5):
     return res
 
 
+def learned_preconditioner(log, seed=5003):
+    """The learned FGMRES preconditioner on a held-out body of the family it
+    was trained on (ellipsoid semi-axes U[0.5, 2], eps_r U[2, 12], 6 x 6 x 6
+    patches of 10 x 10 nodes, plane wave from the seed): plain GMRES, FGMRES
+    with M = D^-1 alone, and FGMRES with the trained network, each to a 1e-4
+    true FP64 residual on the mixed operator."""
+    import numpy as np
+    from paper_2408_02274_amd import precond
+    z = np.load(WEIGHTS)
+    params, dims = z["params"], [int(v) for v in z["dims"]]
+    surf, eps, axes = precond.body(seed)
+    t0 = time.perf_counter()
+    op = precond.make_operator(surf, eps)
+    b = precond.plane_wave_rhs(op, surf, seed)
+    log(f"learned-preconditioner body {seed}: n = {surf.n}, eps_r {eps:.2f}, plan {time.perf_counter() - t0:.1f} s")
+    r = precond.evaluate(op, b, params, dims, rtol=1e-4, maxit=800)
+    op.close()
+    out = {"workload": f"held-out ellipsoid seed {seed}: semi-axes {np.round(axes, 3).tolist()}, eps_r "
+                       f"{eps:.3f}, {surf.n} points, plane wave from the seed",
+           "weights": "paper_2408_02274_amd/weights/precond_nc10.npz"}
+    for k in ("plain", "scaling_only", "learned"):
+        out[k] = {"iters": r[k]["iters"], "seconds": r[k]["wall"], "true_relres": r[k]["true_relres"],
+                  "converged": r[k]["converged"], "fallbacks": r[k]["fallbacks"]}
+    out["learned_vs_plain_seconds"] = r["learned"]["wall"] / r["plain"]["wall"]
+    log(f"learned preconditioner: {out}")
+    return out
+
+
 def kernel_table(st, steps, npts):
     kern = {}
     for name, t in st.get("timing", {}).items():
@@ -171,6 +200,7 @@ def main():
     ap.add_argument("--maxit", type=int, default=400)
     ap.add_argument("--no-fp64-form", action="store_true", help="skip timing the FP64 form beside the mixed one")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-RHS batching measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solves")
     ap.add_argument("--ifgf-only", action="store_true",
                     help="time the raw IFGF sums only (no N-Mueller plan: seconds to set up)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -317,12 +347,11 @@ def main():
         nparams = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
         op.set_preconditioner(np.zeros(nparams, np.float32), dims)
         solve("scaling_only" + ("_mixed" if fp32 else ""))
-        if os.path.exists(WEIGHTS):
-            z = np.load(WEIGHTS)
-            op.set_preconditioner(z["params"], [int(v) for v in z["dims"]])
-            solve("learned" + ("_mixed" if fp32 else ""))
         op.set_preconditioner(None)
 
+    learned = None
+    if not args.no_gmres and not args.no_learned and os.path.exists(WEIGHTS):
+        learned = learned_preconditioner(log)
     res = {
         "metric": METRIC, "value": value, "unit": "matvecs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -340,6 +369,7 @@ def main():
         "fp64_form": fp64_form,
         "gmres_time_to_1e-4_s": (gm.get("mixed") or gm.get("fp64"))["seconds"] if gm else None,
         "gmres": gm,
+        "learned_preconditioner": learned,
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in kern.items()},
     }

@@ -543,7 +543,9 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
     const HostLevel& L = H.lev[d];
     s += std::string(d > 3 ? "," : "") + "{\"d\":" + std::to_string(d) + ",\"boxes\":" +
          std::to_string(L.nb) + ",\"ns\":" + std::to_string(L.ns) + ",\"na\":" +
-         std::to_string(L.na) + ",\"slots\":" + std::to_string(L.nslots) + "}";
+         std::to_string(L.na) + ",\"slots\":" + std::to_string(L.nslots) +
+         ",\"prop_groups\":" + std::to_string(L.pg_off.empty() ? 0 : L.pg_off.back()) +
+         ",\"prop_tiles\":" + std::to_string(L.pt_off.empty() ? 0 : L.pt_off.back()) + "}";
   }
   s += "],\"timing\":{";
   p->timer.collect();

@@ -424,8 +424,10 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 }
 
 // ---------------------------------------------------------------------------
-// interpolation onto cousin targets: thread per target, loop over its cousins
-// blockIdx.y selects the right-hand side r of the batch of R
+// interpolation onto cousin targets: two threads per target, one per
+// wavenumber q (the 16 columns of a cone row split 8 + 8 by kernel); each
+// loops over the target's cousin cones.  blockIdx.y selects the right-hand
+// side r of the batch of R.
 template <int PS, class T, int R>
 __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const double* __restrict__ xs,
                             const double* __restrict__ nrm, int64_t n, double k0, double k1,
@@ -433,23 +435,21 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
   constexpr int NAB = PS * 5;
   constexpr int KS = NAB + (NAB + 3) / 4;
   constexpr int K = 4 * KS;
-  int64_t i = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t i = g >> 1;
+  const int q = (int)(g & 1);
   if (i >= n) return;
   const int64_t e0 = L.tp_off[i], e1 = L.tp_off[i + 1];
   if (e0 == e1) return;
   const T nx = (T)nrm[3 * i], ny = (T)nrm[3 * i + 1], nz = (T)nrm[3 * i + 2];
-  const T kk[2] = {(T)k0, (T)k1};
+  const T kq = (T)(q == 0 ? k0 : k1);
   const int rr = blockIdx.y;
-  double2* o = out_s + ((int64_t)rr * n + i) * 28;
-  T Sr[2][8], Si[2][8], Dr[2][6], Di[2][6];
+  double2* o = out_s + ((int64_t)rr * n + i) * 28 + q * 14;
+  T Sr[8], Si[8], Dr[6], Di[6];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int m = 0; m < 8; ++m) { Sr[m] = (T)0; Si[m] = (T)0; }
 #pragma unroll
-    for (int m = 0; m < 8; ++m) { Sr[q][m] = (T)0; Si[q][m] = (T)0; }
-#pragma unroll
-    for (int m = 0; m < 6; ++m) { Dr[q][m] = (T)0; Di[q][m] = (T)0; }
-  }
-  const T ds = (T)(kEtaD / L.ns), da = (T)(kPiD / L.na);
+  for (int m = 0; m < 6; ++m) { Dr[m] = (T)0; Di[m] = (T)0; }
   for (int64_t e = e0; e < e1; ++e) {
     const int32_t slot = L.tp_slot[e];
     const int32_t B = L.slot_box[slot];
@@ -475,15 +475,17 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
     T c_ph = st > (T)0 ? n_ph / (r * st) : (T)0;     // grad phi = phi-hat / (r sin theta)
     T c_s = -((T)L.h * rinv * rinv) * n_r;           // grad s = -(h / r^2) r-hat
     T c_t = n_th * rinv;                             // grad theta = theta-hat / r
-    c_s *= (T)2 / ds;
-    c_t *= (T)2 / da;
-    c_ph *= (T)2 / da;
-    T F[32], FD[24];
+    c_s *= (T)2 / ((T)(kEtaD / L.ns));
+    c_t *= (T)2 / ((T)(kPiD / L.na));
+    c_ph *= (T)2 / ((T)(kPiD / L.na));
+    // F: interpolant of this kernel's 8 columns (re, im); FD: its n.grad for
+    // the 6 Cartesian densities (re, im)
+    T F[16], FD[12];
 #pragma unroll
-    for (int m = 0; m < 32; ++m) F[m] = (T)0;
+    for (int m = 0; m < 16; ++m) F[m] = (T)0;
 #pragma unroll
-    for (int m = 0; m < 24; ++m) FD[m] = (T)0;
-    const T* Vs = V + (int64_t)slot * K * 32 * R + 32 * rr;
+    for (int m = 0; m < 12; ++m) FD[m] = (T)0;
+    const T* Vs = V + (int64_t)slot * K * 32 * R + 32 * rr + 8 * q;
     // radial index a runs in a rolled loop; Ls/dLs rotate so indices stay static
 #pragma unroll 1
     for (int a = 0; a < PS; ++a) {
@@ -517,51 +519,46 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
           }
           const T* vr = Vs + (int64_t)row * 32 * R;
 #pragma unroll
-          for (int m = 0; m < 32; ++m) F[m] += w * vr[m];
+          for (int m = 0; m < 8; ++m) {
+            F[m] += w * vr[m];
+            F[8 + m] += w * vr[16 + m];
+          }
 #pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-              FD[q * 12 + m] += wd * vr[q * 8 + m];             // real
-              FD[q * 12 + 6 + m] += wd * vr[16 + q * 8 + m];    // imag
-            }
+          for (int m = 0; m < 6; ++m) {
+            FD[m] += wd * vr[m];
+            FD[6 + m] += wd * vr[16 + m];
+          }
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      T sn, cs;
-      tsincos<T>(kk[q] * r, &sn, &cs);
-      const T gr = cs * (T)kInv4PiD * rinv, gi = sn * (T)kInv4PiD * rinv;
-      const T dgr = -rinv * n_r, dgi = kk[q] * n_r;   // (i k - 1/r) n.r-hat
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const T fr = F[q * 8 + m], fi = F[16 + q * 8 + m];
-        Sr[q][m] += gr * fr - gi * fi;
-        Si[q][m] += gr * fi + gi * fr;
-      }
-#pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const T fr = F[q * 8 + m], fi = F[16 + q * 8 + m];
-        const T tr = dgr * fr - dgi * fi + FD[q * 12 + m];
-        const T ti = dgr * fi + dgi * fr + FD[q * 12 + 6 + m];
-        Dr[q][m] += gr * tr - gi * ti;
-        Di[q][m] += gr * ti + gi * tr;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
+    T sn, cs;
+    tsincos<T>(kq * r, &sn, &cs);
+    const T gr = cs * (T)kInv4PiD * rinv, gi = sn * (T)kInv4PiD * rinv;
+    const T dgr = -rinv * n_r, dgi = kq * n_r;   // (i k - 1/r) n.r-hat
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      double2 v = o[q * 14 + m];
-      o[q * 14 + m] = make_double2(v.x + (double)Sr[q][m], v.y + (double)Si[q][m]);
+      const T fr = F[m], fi = F[8 + m];
+      Sr[m] += gr * fr - gi * fi;
+      Si[m] += gr * fi + gi * fr;
     }
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-      double2 v = o[q * 14 + 8 + m];
-      o[q * 14 + 8 + m] = make_double2(v.x + (double)Dr[q][m], v.y + (double)Di[q][m]);
+      const T fr = F[m], fi = F[8 + m];
+      const T tr = dgr * fr - dgi * fi + FD[m];
+      const T ti = dgr * fi + dgi * fr + FD[6 + m];
+      Dr[m] += gr * tr - gi * ti;
+      Di[m] += gr * ti + gi * tr;
     }
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    double2 v = o[m];
+    o[m] = make_double2(v.x + (double)Sr[m], v.y + (double)Si[m]);
+  }
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    double2 v = o[8 + m];
+    o[8 + m] = make_double2(v.x + (double)Dr[m], v.y + (double)Di[m]);
   }
 }
 
@@ -590,7 +587,7 @@ template <int PS, class T, int R>
 hipError_t targets_t(const DevLevel& L, const InterpC& ic, const double* xs, const double* nrm,
                      int64_t n, double k0, double k1, const void* V, double2* out_s, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_targets_k<PS, T, R>), dim3(nblk(n, 64), R), dim3(64), 0, st, L, ic, xs, nrm, n, k0, k1,
+  hipLaunchKernelGGL((k_targets_k<PS, T, R>), dim3(nblk(2 * n, 64), R), dim3(64), 0, st, L, ic, xs, nrm, n, k0, k1,
                      static_cast<const T*>(V), out_s);
   return hipGetLastError();
 }

@@ -235,6 +235,8 @@ def main(argv=None):
                     help="krylov: GMRES residuals as errors e, r = A e; random: i.i.d. e, r = A e; "
                          "mixed: both; trajectory: e_k = y* - x_k, r_k = b - A x_k")
     ap.add_argument("--npairs", type=int, default=200, help="random pairs per body")
+    ap.add_argument("--hidden", default="256,256",
+                    help="hidden widths, comma separated, or 'none' for a single affine layer")
     args = ap.parse_args(argv)
     import torch
 
@@ -244,7 +246,8 @@ def main(argv=None):
         for i in range(args.bodies):
             seed = TRAIN_SEED0 + i
             surf, eps, axes = body(seed)
-            dims = dims_for(surf.nc)
+            hidden = () if args.hidden == "none" else tuple(int(h) for h in args.hidden.split(","))
+            dims = dims_for(surf.nc, hidden)
             t0 = time.perf_counter()
             op = make_operator(surf, eps)
             _log(f"body {seed}: axes {np.round(axes, 2).tolist()} eps {eps:.2f}, plan {time.perf_counter() - t0:.1f} s")

@@ -269,3 +269,27 @@ def test_fgmres_with_scaling_preconditioner_and_fallbacks():
     rel = float(torch.linalg.norm(b - op.apply(y3)) / torch.linalg.norm(b))
     assert rel <= 1e-5
     op.close()
+
+
+def test_trained_preconditioner_gain_on_held_out_body():
+    """The committed network (trained on operator-generated pairs of the
+    ellipsoid family, seeds 6000+) on held-out body 5002: flexible GMRES with
+    it needs fewer iterations than plain GMRES to the same FP64 true
+    residual; M = D^-1 alone is reported beside it (it does better still)."""
+    import os
+    from paper_2408_02274_amd import precond
+    path = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_2408_02274_amd", "weights",
+                        "precond_nc10.npz")
+    z = np.load(path)
+    params, dims = z["params"], [int(v) for v in z["dims"]]
+    surf, eps, axes = precond.body(5002)
+    _say(f"[gpu] trained preconditioner, body 5002: n = {surf.n}, eps {eps:.2f}")
+    op = precond.make_operator(surf, eps)
+    b = precond.plane_wave_rhs(op, surf, 5002)
+    r = precond.evaluate(op, b, params, dims, rtol=1e-4, maxit=800)
+    _say({k: (r[k]["iters"], round(r[k]["wall"], 2), r[k]["fallbacks"]) for k in ("plain", "scaling_only", "learned")})
+    for k in ("plain", "scaling_only", "learned"):
+        assert r[k]["converged"] and r[k]["true_relres"] <= 1e-4
+    assert r["learned"]["fallbacks"] == 0
+    assert r["learned"]["iters"] < r["plain"]["iters"]
+    op.close()
