@@ -69,3 +69,25 @@ def test_direct_target_subset():
     idx = np.array([0, 5, 17, 40])
     sub = direct.regular_sums(s.x, s.normal, w, phi, (2.0, 3.0), targets=idx)
     assert np.allclose(sub, full[:, :, idx], rtol=1e-14, atol=1e-15)
+
+
+def test_rounded_box_area_and_volume_closed_forms():
+    """The rounded-box generator (the waveguide stand-in) against Steiner's
+    formulas for the Minkowski sum of a box (edges A, B, C) and a ball of
+    radius r: area 2(AB+BC+CA) + 2 pi r (A+B+C) + 4 pi r^2; volume
+    ABC + 2 r (AB+BC+CA) + pi r^2 (A+B+C) + 4/3 pi r^3 (divergence theorem:
+    the integral of x.n is 3 V); the integral of n vanishes."""
+    import synth
+    from oracle.surface import PatchSurface
+    r = 0.1
+    s = synth.rounded_box((2.0, 0.5, 0.25), r, 0.3, 10)
+    surf = PatchSurface(s.P, s.nc, s.x, s.du, s.dv)
+    A, B, C = 2 * (2.0 - r), 2 * (0.5 - r), 2 * (0.25 - r)
+    area = 2 * (A * B + B * C + C * A) + 2 * np.pi * r * (A + B + C) + 4 * np.pi * r * r
+    vol = A * B * C + 2 * r * (A * B + B * C + C * A) + np.pi * r * r * (A + B + C) + 4.0 / 3.0 * np.pi * r ** 3
+    assert abs(surf.w.sum() - area) < 1e-9 * area
+    flux = np.sum(surf.w * np.sum(s.x * s.normal, axis=1))
+    assert abs(flux - 3 * vol) < 2e-9 * 3 * vol
+    assert np.max(np.abs((surf.w[:, None] * s.normal).sum(0))) < 1e-9 * area
+    # outward normals agree with the patch orientation
+    assert np.all(np.sum(surf.n * s.normal, axis=1) > 0.999)
