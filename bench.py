@@ -65,10 +65,11 @@ def kernel_sha(path=KERNEL_SRC):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_per_launch(kernel, precision):
+def traffic_per_launch(kernel, precision, points, Ps, Pa):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when there is none for this kernel and precision or the
-    kernel source changed since the counters were taken."""
+    summary, or None when there is none for this kernel, precision and
+    workload (points, orders) or the kernel source changed since the counters
+    were taken."""
     if not os.path.exists(TRAFFIC):
         return None
     vals = {}
@@ -77,6 +78,8 @@ def traffic_per_launch(kernel, precision):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel") != kernel or vals.get("precision") != precision:
+        return None
+    if vals.get("points") != str(points) or vals.get("orders") != f"{Ps},{Pa}":
         return None
     if vals.get("kernel_source_sha256") != kernel_sha():
         return None
@@ -192,6 +195,7 @@ def main():
                     help="IFGF form of the timed steps: fp32 = mixed (default), fp64 = plain")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--npf", type=int, default=16, help="patches per cube face edge")
+    ap.add_argument("--nc", type=int, default=10, help="Chebyshev nodes per patch direction")
     ap.add_argument("--radius", type=float, default=5.0)
     ap.add_argument("--cpu-rows", type=int, default=1536)
     ap.add_argument("--no-cpu", action="store_true")
@@ -230,7 +234,7 @@ def main():
         log(f"copy calibration: {nb} bytes read, {nb} bytes written")
         del src, dst
 
-    surf = synth.cube_sphere(args.npf, 10, args.radius)
+    surf = synth.cube_sphere(args.npf, args.nc, args.radius)
     eps_e, eps_i = 1.0, 2.25
     fp32 = args.precision == "fp32"
     prec = B.IFGF_FP32 if fp32 else B.IFGF_FP64
@@ -307,7 +311,7 @@ def main():
         achieved = d["bytes"] / (d["ms"] * 1e-3)
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": 8000.0,
                 "unit": "GB/s", "frac": achieved / PEAK["hbm"]}
-    tr = traffic_per_launch(dom, args.precision)
+    tr = traffic_per_launch(dom, args.precision, surf.n, st["Ps"], st["Pa"]) if args.nrhs == 1 else None
     roof["traffic"] = tr
     if tr is not None:
         roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
@@ -361,7 +365,7 @@ def main():
         "config": {"workload": ("IFGF raw sums only: " if args.ifgf_only else "") +
                                f"N-Mueller forward map, dielectric sphere radius {args.radius} "
                                f"(eps_r 2.25 in vacuum, k_int = 3 pi, k_ext = 2 pi), 6x{args.npf}x{args.npf} "
-                               f"patches x 10x10 Chebyshev nodes ({surf.n} points, {4 * surf.n} unknowns), "
+                               f"patches x {args.nc}x{args.nc} Chebyshev nodes ({surf.n} points, {4 * surf.n} unknowns), "
                                f"IFGF tol {args.tol}, {args.nrhs} RHS per step, "
                                + ("mixed: FP32 IFGF, FP64 corrections/assembly/GMRES" if fp32 else "FP64"),
                    "Ps": st["Ps"], "Pa": st["Pa"], "D": st["D"], "plan_seconds": round(plan_s, 2),
