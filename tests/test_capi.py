@@ -120,3 +120,13 @@ def test_pair_tables_equal_oracle(case):
                 assert np.array_equal(binding.ifgf_plan_table(h, 3000 + d - 1), want)
     finally:
         binding.ifgf_destroy(h)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    """No CPU fallback: a missing libifgf.so is an ImportError, not a
+    silent switch to another implementation."""
+    import paper_2408_02274_amd.binding as B
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libifgf.so"))
+    with pytest.raises(ImportError):
+        B.lib()

@@ -142,3 +142,20 @@ def test_precision_switch_reproduces_fp64_plan():
         B.ifgf_set_precision(p64.handle, 7)
     p32.close()
     p64.close()
+
+
+@pytest.mark.parametrize("order", [(4, 6), (5, 7)])
+def test_fp64_scalar_path_matches_reference_ifgf(order):
+    """Orders with Pa != 5 run the FP64 kernels with one thread per point
+    (no matrix cores); same bar against the step-by-step reference IFGF."""
+    s, ks = CASES["sphere864"]()
+    rng = np.random.default_rng(23)
+    w = rng.uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 24)
+    Ps, Pa = order
+    _say(f"[gpu] ifgf fp64 scalar path n={s.n} Ps={Ps} Pa={Pa}")
+    g = _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa)[0]
+    o2 = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params(Ps=Ps, Pa=Pa)).apply(phi[0])
+    for q in range(2):
+        assert _rel(g[q, :8], o2[q, :8]) < 1e-10
+        assert _rel(g[q, 8:], o2[q, 8:]) < 1e-10
