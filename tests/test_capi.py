@@ -130,3 +130,26 @@ def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libifgf.so"))
     with pytest.raises(ImportError):
         B.lib()
+
+
+def test_literal_radial_refinement_tables_equal_oracle():
+    """refine_radial = 1 (both cone counts doubled per level, the literal
+    rule of Remark 2): cone counts per level and relevant-cone tables equal
+    the oracle's, and the radial count really grows."""
+    s = synth.cube_sphere(2, 6)
+    ks = (1.5 * math.pi, math.pi)
+    h = binding.ifgf_plan(s.x, s.normal, np.ones(s.n), ks[0], ks[1], 1e-3, Ps=3, Pa=5,
+                          refine_radial=1, host_only=1)
+    try:
+        t = ifgf_ref.Tree(s.x, ks, ifgf_ref.Params(Ps=3, Pa=5, refine_radial=True))
+        c = binding.ifgf_plan_counts(h)
+        assert c[1] == t.D
+        grew = False
+        for i, d in enumerate(range(3, t.D + 1)):
+            nsna = c[7 + 4 * i + 3]
+            assert (nsna >> 16, nsna & 0xFFFF) == (t.ns[d], t.na[d])
+            grew |= t.ns[d] > 1
+            assert np.array_equal(binding.ifgf_plan_table(h, 1000 + d), t.levels[d].slot_key)
+        assert grew
+    finally:
+        binding.ifgf_destroy(h)

@@ -159,3 +159,21 @@ def test_fp64_scalar_path_matches_reference_ifgf(order):
     for q in range(2):
         assert _rel(g[q, :8], o2[q, :8]) < 1e-10
         assert _rel(g[q, 8:], o2[q, 8:]) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_literal_radial_refinement_matches_reference(prec):
+    """refine_radial = 1 through the matrix-core kernels (n_s > 1 cones)."""
+    from paper_2408_02274_amd import binding as B
+    s, ks = CASES["sphere864"]()
+    rng = np.random.default_rng(25)
+    w = rng.uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 26)
+    _say(f"[gpu] ifgf refine_radial {prec}")
+    p = B.IFGF_FP64 if prec == "fp64" else B.IFGF_FP32
+    g = _gpu_apply(s.x, s.normal, w, ks, phi, Ps=3, Pa=5, refine_radial=1, precision=p)[0]
+    o2 = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params(Ps=3, Pa=5, refine_radial=True)).apply(phi[0])
+    bar = (1e-10, 1e-10) if prec == "fp64" else (2e-5, 1e-4)
+    for q in range(2):
+        assert _rel(g[q, :8], o2[q, :8]) < bar[0]
+        assert _rel(g[q, 8:], o2[q, 8:]) < bar[1]
