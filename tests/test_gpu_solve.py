@@ -84,3 +84,26 @@ def test_mixed_precision_solve_meets_fp64_residual():
     assert abs(rel64 - info[0]["true_relres"]) < 1e-9
     op32.close()
     op64.close()
+
+
+def test_table1_row1_forward_map_error_against_paper():
+    """Table I row 1 (6,144 points, Nc = 16, k_i = 3 pi, (Ps, Pa) = (3, 5)):
+    with the literal cone rule (radial and angular counts doubled, as the
+    paper's runs evidently were) the forward-map error against a tol = 1e-10
+    plan is of the paper's order of magnitude (the test vector is not the
+    paper's, so only the order is compared)."""
+    from paper_2408_02274_amd import NMullerOperator
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_table1_row1.json")))
+    s = synth.cube_sphere(2, 16, 1.0)
+    assert s.n == gold["N"]
+    y = torch.from_numpy(synth.complex_normal((1, 4, s.n), 1)).to("cuda")
+    _say("[gpu] Table I row 1: reference plan tol 1e-10")
+    ref_op = NMullerOperator(s, 1.0, 2.25, tol=1e-10)
+    ref = ref_op.apply(y)
+    ref_op.close()
+    _say("[gpu] Table I row 1: (3, 5) literal cone rule")
+    op = NMullerOperator(s, 1.0, 2.25, tol=1e-3, Ps=3, Pa=5, refine_radial=1)
+    err = float(torch.linalg.norm(op.apply(y) - ref) / torch.linalg.norm(ref))
+    op.close()
+    _say(err, gold["err_fm"])
+    assert gold["err_fm"] / 3 < err < 3 * gold["err_fm"]

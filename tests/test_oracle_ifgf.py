@@ -138,3 +138,21 @@ def test_relevant_cone_invariants(small_case):
             rc = np.sqrt(np.sum((X - L.centers[cbox]) ** 2, axis=1))
             # parent interpolation points lie at s_child <= sqrt(3)/2 / (3 - sqrt(3)/2)
             assert np.all(L.h / rc <= (math.sqrt(3) / 2) / (3 - math.sqrt(3) / 2) + 1e-12)
+
+
+def test_vectorised_sums_equal_single_density_runs(small_case):
+    """IFGF_Vec (all 16 density x kernel columns through one cone structure,
+    Sec. III-I) equals one run per density with the others zero (IFGF_Seq)."""
+    s, w, phi, ks = small_case
+    ref = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params())
+    full = ref.apply(phi)
+    for c in range(8):
+        one = np.zeros_like(phi)
+        one[c] = phi[c]
+        out = ref.apply(one)
+        scale = np.max(np.abs(full[:, c]))
+        assert np.max(np.abs(out[:, c] - full[:, c])) < 1e-13 * scale
+        if c < 6:
+            assert np.max(np.abs(out[:, 8 + c] - full[:, 8 + c])) < 1e-13 * np.max(np.abs(full[:, 8 + c]))
+        others = [k for k in range(8) if k != c]
+        assert np.max(np.abs(out[:, others])) == 0.0
