@@ -95,6 +95,8 @@ struct ifgf_plan_s {
   int rcap = 1;                         // right-hand sides per pass the buffers hold
   int rsel = 1;                         // right-hand sides per pass in use (<= rcap)
   std::vector<PropGroups> groups;       // groups[d]: propagation into level d
+  std::vector<TargetTiles> ttiles;      // ttiles[d]: target pairs by cone (matrix-core interpolation)
+  void* d_res = nullptr;                // per-pair target contributions [pairs][28] complex
 };
 
 namespace ifgf {
@@ -276,6 +278,8 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   if (p->mfma)
     for (int d = 1; d <= H.D; ++d) std::vector<int32_t>().swap(H.lev[d].pp_slot);
   p->groups.assign(H.D + 1, PropGroups());
+  p->ttiles.assign(H.D + 1, TargetTiles());
+  int64_t max_pairs = 0;
   p->lev.assign(H.D + 1, DevLevel());
   for (int d = 1; d <= H.D; ++d) {
     HostLevel& L = H.lev[d];
@@ -331,6 +335,29 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
       std::vector<int32_t>().swap(L.pg_count);
       std::vector<uint8_t>().swap(L.pg_pts);
     }
+    if (p->mfma && d >= 3 && !L.tt_slot.empty()) {
+      TargetTiles& TT = p->ttiles[d];
+      int32_t *sl = nullptr, *tg = nullptr, *ee = nullptr;
+      int64_t* stt = nullptr;
+      uint8_t* cn = nullptr;
+      if ((rc = upload(ar, L.tt_slot, &sl)) || (rc = upload(ar, L.tt_start, &stt)) ||
+          (rc = upload(ar, L.tt_cnt, &cn)) || (rc = upload(ar, L.ts_tgt, &tg)) || (rc = upload(ar, L.ts_e, &ee))) {
+        delete p;
+        return rc;
+      }
+      TT.ntiles = (int64_t)L.tt_slot.size();
+      TT.slot = sl;
+      TT.start = stt;
+      TT.cnt = cn;
+      TT.tgt = tg;
+      TT.e = ee;
+      max_pairs = std::max(max_pairs, L.tp_off.back());
+    }
+    std::vector<int32_t>().swap(L.tt_slot);
+    std::vector<int64_t>().swap(L.tt_start);
+    std::vector<uint8_t>().swap(L.tt_cnt);
+    std::vector<int32_t>().swap(L.ts_tgt);
+    std::vector<int32_t>().swap(L.ts_e);
     if (d >= 3) p->max_slots = std::max(p->max_slots, L.nslots);
     // the host copies of the large pair tables are no longer needed
     std::vector<int32_t>().swap(L.tp_slot);
@@ -351,6 +378,13 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   if (p->mfma) {
     p->d_af = ar.alloc(sizeof(double) * 16 * (size_t)n * p->rcap);
     if (!p->d_af) {
+      delete p;
+      return set_error(IFGF_ENOMEM, "device workspace allocation failed");
+    }
+  }
+  if (max_pairs > 0) {
+    p->d_res = ar.alloc(sizeof(double) * 56 * (size_t)max_pairs);
+    if (!p->d_res) {
       delete p;
       return set_error(IFGF_ENOMEM, "device workspace allocation failed");
     }
@@ -411,9 +445,16 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
       T.end("leaf", ev, st, (double)H.leaf_pairs * R);
       for (int d = H.D; d >= 3; --d) {
         ev = T.begin(st);
-        if ((e = mf_targets(p->fp32, H.Ps, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1, p->d_vals[cur],
-                            p->d_out_s, st)) != hipSuccess)
+        if (R == 1 && p->d_res && p->ttiles[d].ntiles > 0) {
+          // cone-major tiles on the matrix cores, then the per-target sums
+          if ((e = mf_targets_tiles(p->fp32, H.Ps, p->lev[d], p->ic, p->ttiles[d], p->d_xs, p->d_nrm, k0, k1,
+                                    p->d_vals[cur], p->d_res, st)) != hipSuccess ||
+              (e = mf_targets_reduce(p->fp32, p->lev[d], n, p->d_res, p->d_out_s, st)) != hipSuccess)
+            return set_hip_error(e, "targets");
+        } else if ((e = mf_targets(p->fp32, H.Ps, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1,
+                                   p->d_vals[cur], p->d_out_s, st)) != hipSuccess) {
           return set_hip_error(e, "targets");
+        }
         T.end("targets", ev, st, (double)H.lev[d].tp_off.back() * R);
         if (d > 3) {
           ev = T.begin(st);

@@ -562,6 +562,188 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// interpolation onto cousin targets on the matrix cores: one wavefront per
+// tile of up to 8 targets that fall in one cone.  MFMA row 2t carries the
+// interpolation weights of target t, row 2t + 1 the weights of the normal
+// derivative of the interpolant (chain rule through (s, theta, phi)); both
+// are contracted with the cone's 32 value columns at once.  The epilogue
+// applies the centred factor G(x, x_B) and its gradient and writes the 28
+// complex contributions of each (target, cousin) pair to res; a second
+// kernel sums them per target.
+template <int PS, class T>
+__global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, TargetTiles TT,
+                                                      const double* __restrict__ xs,
+                                                      const double* __restrict__ nrm, double k0, double k1,
+                                                      const T* __restrict__ V, T* __restrict__ res) {
+  constexpr int NAB = PS * 5;
+  constexpr int KS = NAB + (NAB + 3) / 4;
+  constexpr int K = 4 * KS;
+  // per-target record: Ls, c_s dLs, Lt, c_t dLt, Lp, c_ph dLp, then
+  // Re G_q, Im G_q (q = 0, 1), -n.r-hat / r, n.r-hat
+  constexpr int OLS = 0, OSD = PS, OLT = 2 * PS, OTD = 2 * PS + 5, OLP = 2 * PS + 10, OPD = 2 * PS + 15,
+                OG = 2 * PS + 20, TW = 2 * PS + 26;
+  __shared__ T rec[4][8][TW];
+  __shared__ T outb[4][16][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, gl = lane >> 4;
+  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= TT.ntiles) return;   // whole wavefront; only wavefront barriers follow
+  const int32_t slot = TT.slot[tile];
+  const int64_t kbeg = TT.start[tile];
+  const int cnt = TT.cnt[tile];
+  const int cone = L.slot_cone[slot];
+  const double* c = L.centers + 3 * L.slot_box[slot];
+  T(*rw)[TW] = rec[wave];
+  if (lane < 8) {
+    T* o = rw[lane];
+    if (lane < cnt) {
+      const int64_t i = TT.tgt[kbeg + lane];
+      const T nx = (T)nrm[3 * i], ny = (T)nrm[3 * i + 1], nz = (T)nrm[3 * i + 2];
+      const T zx = (T)(xs[3 * i] - c[0]), zy = (T)(xs[3 * i + 1] - c[1]), zz = (T)(xs[3 * i + 2] - c[2]);
+      T r, us, ut, up, th, ph;
+      local3<T>(zx, zy, zz, (T)L.h, L.ns, L.na, cone, &r, &us, &ut, &up, &th, &ph);
+      T Ls[PS], Lt[5], Lp[5], dLs[PS], dLt[5], dLp[5];
+      lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, Ls);
+      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
+      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
+      lag_d<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, dLs);
+      lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, dLt);
+      lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, dLp);
+      const T rinv = (T)1 / r;
+      const T n_r = (nx * zx + ny * zy + nz * zz) * rinv;
+      T sth, cth, sph, cph;
+      tsincos<T>(th, &sth, &cth);
+      tsincos<T>(ph, &sph, &cph);
+      const T n_th = nx * cth * cph + ny * cth * sph - nz * sth;
+      const T n_ph = -nx * sph + ny * cph;
+      T c_ph = sth > (T)0 ? n_ph / (r * sth) : (T)0;   // grad phi = phi-hat / (r sin theta)
+      T c_s = -((T)L.h * rinv * rinv) * n_r;           // grad s = -(h / r^2) r-hat
+      T c_t = n_th * rinv;                             // grad theta = theta-hat / r
+      c_s *= (T)2 / ((T)(kEtaD / L.ns));
+      c_t *= (T)2 / ((T)(kPiD / L.na));
+      c_ph *= (T)2 / ((T)(kPiD / L.na));
+#pragma unroll
+      for (int z = 0; z < PS; ++z) {
+        o[OLS + z] = Ls[z];
+        o[OSD + z] = c_s * dLs[z];
+      }
+#pragma unroll
+      for (int z = 0; z < 5; ++z) {
+        o[OLT + z] = Lt[z];
+        o[OTD + z] = c_t * dLt[z];
+        o[OLP + z] = Lp[z];
+        o[OPD + z] = c_ph * dLp[z];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        T sn, cs;
+        tsincos<T>((T)(q == 0 ? k0 : k1) * r, &sn, &cs);
+        o[OG + q] = cs * (T)kInv4PiD * rinv;
+        o[OG + 2 + q] = sn * (T)kInv4PiD * rinv;
+      }
+      o[OG + 4] = -rinv * n_r;
+      o[OG + 5] = n_r;
+    } else {
+      for (int z = 0; z < TW; ++z) o[z] = (T)0;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // A operand of row r16 (target t, value or derivative) at node (a, b, c):
+  //   value:      Ls[a] Lt[b] Lp[c]
+  //   derivative: (c_s dLs[a]) Lt[b] Lp[c] + Ls[a] (c_t dLt[b]) Lp[c] + Ls[a] Lt[b] (c_ph dLp[c])
+  // = Lt[b] U[a] + (c_t dLt[b]) W[a] with per-lane U, W for the phi-node c
+  const int t = r16 >> 1;
+  const T kv = (r16 & 1) ? (T)0 : (T)1, kd = (T)1 - kv;
+  const T* me = rw[t];
+  T U[PS], W[PS], Ltv[5], Tdv[5];
+  {
+    const T f1 = kv * me[OLP + gl] + kd * me[OPD + gl], f2 = kd * me[OLP + gl];
+#pragma unroll
+    for (int a = 0; a < PS; ++a) {
+      U[a] = me[OLS + a] * f1 + me[OSD + a] * f2;
+      W[a] = me[OLS + a] * f2;
+    }
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      Ltv[b] = me[OLT + b];
+      Tdv[b] = me[OTD + b];
+    }
+  }
+  const T g1 = kv * me[OLP + 4] + kd * me[OPD + 4], g2 = kd * me[OLP + 4];
+  typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+  const T* Vs = V + (int64_t)slot * K * 32 + gl * 32;
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    T av;
+    if (j < NAB) {
+      av = Ltv[j % 5] * U[j / 5] + Tdv[j % 5] * W[j / 5];   // (a, b) = j, phi-node gl
+    } else {
+      const int ab = 4 * (j - NAB) + gl;                   // phi-node 4 of pair ab
+      if (ab < NAB) {
+        const T lsa = me[OLS + ab / 5], sda = me[OSD + ab / 5];
+        av = me[OLT + ab % 5] * (lsa * g1 + sda * g2) + me[OTD + ab % 5] * lsa * g2;
+      } else {
+        av = (T)0;
+      }
+    }
+    const T* vrow = Vs + (int64_t)(4 * j) * 32;
+    c0 = MF<T>::mma(av, vrow[r16], c0);
+    c1 = MF<T>::mma(av, vrow[16 + r16], c1);
+  }
+  T(*ob)[33] = outb[wave];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = MF<T>::row(lane, e);
+    ob[row][r16] = c0[e];
+    ob[row][16 + r16] = c1[e];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // epilogue: lane -> target lane / 8, density m = lane % 8, both kernels
+  const int tt = lane >> 3, m = lane & 7;
+  if (tt < cnt) {
+    const int64_t e = TT.e[kbeg + tt];
+    const T* g = rw[tt] + OG;
+    T* out = res + e * 56;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int col = 8 * q + m;
+      const T fr = ob[2 * tt][col], fi = ob[2 * tt][16 + col];
+      const T gr = g[q], gi = g[2 + q];
+      out[2 * (14 * q + m)] = gr * fr - gi * fi;
+      out[2 * (14 * q + m) + 1] = gr * fi + gi * fr;
+      if (m < 6) {
+        const T dr = ob[2 * tt + 1][col], di = ob[2 * tt + 1][16 + col];
+        const T dgr = g[4], dgi = (T)(q == 0 ? k0 : k1) * g[5];   // (i k - 1/r) n.r-hat
+        const T tr = dgr * fr - dgi * fi + dr, ti = dgr * fi + dgi * fr + di;
+        out[2 * (14 * q + 8 + m)] = gr * tr - gi * ti;
+        out[2 * (14 * q + 8 + m) + 1] = gr * ti + gi * tr;
+      }
+    }
+  }
+}
+
+// out_s[i][k] += sum over the target pairs e of i of res[e][k], k < 28 (FP64 sums)
+template <class T>
+__global__ void __launch_bounds__(256) k_targets_reduce(const int64_t* __restrict__ tp_off, int64_t n,
+                                                        const T* __restrict__ res, double2* __restrict__ out_s) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * 28) return;
+  const int64_t i = g / 28;
+  const int k = (int)(g % 28);
+  double re = 0.0, im = 0.0;
+  for (int64_t e = tp_off[i]; e < tp_off[i + 1]; ++e) {
+    re += (double)res[e * 56 + 2 * k];
+    im += (double)res[e * 56 + 2 * k + 1];
+  }
+  const double2 v = out_s[g];
+  out_s[g] = make_double2(v.x + re, v.y + im);
+}
+
 inline unsigned nblk(int64_t w, int bs) { return (unsigned)((w + bs - 1) / bs); }
 
 template <int PS, class T, int R>
@@ -668,6 +850,27 @@ hipError_t dispatch_targets(int Ps, int R, const DevLevel& L, const InterpC& ic,
   return hipErrorInvalidValue;
 }
 
+template <int PS, class T>
+hipError_t targets_tiles_t(const DevLevel& L, const InterpC& ic, const TargetTiles& TT, const double* xs,
+                           const double* nrm, double k0, double k1, const void* V, void* res, hipStream_t st) {
+  if (TT.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_targets_mfma<PS, T>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT, xs, nrm, k0,
+                     k1, static_cast<const T*>(V), static_cast<T*>(res));
+  return hipGetLastError();
+}
+template <class T>
+hipError_t dispatch_targets_tiles(int Ps, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
+                                  const double* xs, const double* nrm, double k0, double k1, const void* V,
+                                  void* res, hipStream_t st) {
+  switch (Ps) {
+    case 3: return targets_tiles_t<3, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
+    case 4: return targets_tiles_t<4, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
+    case 5: return targets_tiles_t<5, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
+    case 6: return targets_tiles_t<6, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 bool mfma_path_supported(int Ps, int Pa) { return Pa == 5 && Ps >= 3 && Ps <= 6; }
@@ -709,6 +912,25 @@ hipError_t mf_targets(bool fp32, int Ps, int R, const DevLevel& L, const InterpC
                       double2* out_s, hipStream_t st) {
   return fp32 ? dispatch_targets<float>(Ps, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st)
               : dispatch_targets<double>(Ps, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+}
+
+hipError_t mf_targets_tiles(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
+                            const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
+                            hipStream_t st) {
+  return fp32 ? dispatch_targets_tiles<float>(Ps, L, ic, TT, xs, nrm, k0, k1, V, res, st)
+              : dispatch_targets_tiles<double>(Ps, L, ic, TT, xs, nrm, k0, k1, V, res, st);
+}
+
+hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_targets_reduce<float>, dim3(nblk(n * 28, 256)), dim3(256), 0, st, L.tp_off, n,
+                       static_cast<const float*>(res), out_s);
+  else
+    hipLaunchKernelGGL(k_targets_reduce<double>, dim3(nblk(n * 28, 256)), dim3(256), 0, st, L.tp_off, n,
+                       static_cast<const double*>(res), out_s);
+  return hipGetLastError();
 }
 
 }  // namespace ifgf

@@ -25,6 +25,18 @@ struct PropGroups {
   const uint8_t* tt0 = nullptr;    // first point (within the group) of each tile
 };
 
+// Target pairs of one level grouped by cone slot, in tiles of at most 8
+// targets: tile t covers entries [start[t], start[t] + cnt[t]) of tgt (sorted
+// target) and e (the pair's index in the target-major pair list).
+struct TargetTiles {
+  int64_t ntiles = 0;
+  const int32_t* slot = nullptr;
+  const int64_t* start = nullptr;
+  const uint8_t* cnt = nullptr;
+  const int32_t* tgt = nullptr;
+  const int32_t* e = nullptr;
+};
+
 bool mfma_path_supported(int Ps, int Pa);
 int kslot_rows(int Ps);   // rows per cone in K-slot order
 // Right-hand sides per pass: cone rows hold R groups of 32 reals, R in {1, 2, 4}
@@ -43,5 +55,14 @@ hipError_t mf_propagate(bool fp32, int Ps, int R, const DevLevel& C, const DevLe
 hipError_t mf_targets(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                       const double* nrm, int64_t n, double k0, double k1, const void* V,
                       double2* out_s, hipStream_t st);
+
+// Target interpolation on the matrix cores (one right-hand side): per pair e
+// the 28 complex contributions into res [pairs][28] (complex in the cone
+// precision), then out_s[i] += sum of res over the pairs of target i.
+hipError_t mf_targets_tiles(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
+                            const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
+                            hipStream_t st);
+hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,
+                             hipStream_t st);
 
 }  // namespace ifgf

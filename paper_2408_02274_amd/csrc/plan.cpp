@@ -95,6 +95,32 @@ static int find_slot(const HostLevel& L, int64_t box, int cone) {
   return (int)(L.slot_off[box] + (it - b));
 }
 
+void build_target_tiles(HostLevel& L, int64_t n) {
+  const int64_t np = L.tp_off.empty() ? 0 : L.tp_off[n];
+  if (np <= 0 || np >= ((int64_t)1 << 31) || L.nslots <= 0) return;
+  std::vector<int64_t> off(L.nslots + 1, 0);
+  for (int64_t e = 0; e < np; ++e) off[L.tp_slot[e] + 1] += 1;
+  for (int64_t s = 0; s < L.nslots; ++s) off[s + 1] += off[s];
+  std::vector<int64_t> cur(off.begin(), off.end() - 1);
+  L.ts_tgt.resize(np);
+  L.ts_e.resize(np);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = L.tp_off[i]; e < L.tp_off[i + 1]; ++e) {
+      const int64_t pos = cur[L.tp_slot[e]]++;
+      L.ts_tgt[pos] = (int32_t)i;
+      L.ts_e[pos] = (int32_t)e;
+    }
+  L.tt_slot.clear();
+  L.tt_start.clear();
+  L.tt_cnt.clear();
+  for (int64_t s = 0; s < L.nslots; ++s)
+    for (int64_t k = off[s]; k < off[s + 1]; k += 8) {
+      L.tt_slot.push_back((int32_t)s);
+      L.tt_start.push_back(k);
+      L.tt_cnt.push_back((uint8_t)std::min<int64_t>(8, off[s + 1] - k));
+    }
+}
+
 void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts) {
   const int64_t Q = Pl.nslots;
   std::vector<std::vector<int32_t>> gs(Q), gc(Q), gn(Q);
@@ -406,6 +432,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
       }
     }
     if (bad) { err = "internal: cousin target outside relevant cones"; return -1; }
+    build_target_tiles(L, n);
     // propagation pairs into level d-1
     if (d >= 4) {
       HostLevel& Pl = P.lev[d - 1];

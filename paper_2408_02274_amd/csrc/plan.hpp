@@ -50,6 +50,14 @@ struct HostLevel {
   std::vector<int64_t> pt_off;
   std::vector<int32_t> pt_g;
   std::vector<uint8_t> pt_t0;
+  // the target pairs grouped by cone slot (targets ascending within a slot),
+  // cut into tiles of at most 8 targets: tile t covers entries
+  // [tt_start[t], tt_start[t] + tt_cnt[t]) of ts_tgt (sorted target) and
+  // ts_e (its index in the target-major pair list), all of slot tt_slot[t]
+  std::vector<int32_t> ts_tgt, ts_e;
+  std::vector<int32_t> tt_slot;
+  std::vector<int64_t> tt_start;
+  std::vector<uint8_t> tt_cnt;
 };
 
 struct HostPlan {
@@ -76,6 +84,10 @@ struct PlanParams {
 int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
                     const double* w, double k0, double k1, const PlanParams& pp,
                     std::string& err);
+
+// Group the target pairs of level L by cone slot and cut them into tiles of
+// at most 8 targets (requires fewer than 2^31 pairs; else leaves them empty).
+void build_target_tiles(HostLevel& L, int64_t n);
 
 // Group the propagation pairs of parent level Pl (children at level L) by
 // child cone slot (requires npts <= 256).
