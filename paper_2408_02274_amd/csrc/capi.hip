@@ -307,34 +307,26 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     }
     if (p->mfma && !L.pg_off.empty()) {
       PropGroups& PG = p->groups[d];
-      int64_t *o = nullptr, *st = nullptr, *to = nullptr;
-      int32_t *sl = nullptr, *cb = nullptr, *cn = nullptr, *tgp = nullptr;
-      uint8_t *pt = nullptr, *tt = nullptr;
-      if ((rc = upload(ar, L.pg_off, &o)) || (rc = upload(ar, L.pg_start, &st)) ||
-          (rc = upload(ar, L.pg_slot, &sl)) || (rc = upload(ar, L.pg_cbox, &cb)) ||
-          (rc = upload(ar, L.pg_count, &cn)) || (rc = upload(ar, L.pg_pts, &pt)) ||
-          (rc = upload(ar, L.pt_off, &to)) || (rc = upload(ar, L.pt_g, &tgp)) ||
-          (rc = upload(ar, L.pt_t0, &tt))) {
+      int64_t* to = nullptr;
+      int32_t* rec = nullptr;
+      uint8_t* pt = nullptr;
+      if ((rc = upload(ar, L.pt_off, &to)) || (rc = upload(ar, L.pt_rec, &rec)) || (rc = upload(ar, L.pg_pts, &pt))) {
         delete p;
         return rc;
       }
       PG.toff = to;
-      PG.tg = tgp;
-      PG.tt0 = tt;
-      std::vector<int32_t>().swap(L.pt_g);
-      std::vector<uint8_t>().swap(L.pt_t0);
-      PG.off = o;
-      PG.start = st;
-      PG.slot = sl;
-      PG.cbox = cb;
-      PG.count = cn;
+      PG.rec = reinterpret_cast<const int4*>(rec);
       PG.pts = pt;
-      std::vector<int64_t>().swap(L.pg_start);
-      std::vector<int32_t>().swap(L.pg_slot);
-      std::vector<int32_t>().swap(L.pg_cbox);
-      std::vector<int32_t>().swap(L.pg_count);
-      std::vector<uint8_t>().swap(L.pg_pts);
     }
+    // only the offsets stay on the host (statistics)
+    std::vector<int32_t>().swap(L.pt_rec);
+    std::vector<int32_t>().swap(L.pt_g);
+    std::vector<uint8_t>().swap(L.pt_t0);
+    std::vector<int64_t>().swap(L.pg_start);
+    std::vector<int32_t>().swap(L.pg_slot);
+    std::vector<int32_t>().swap(L.pg_cbox);
+    std::vector<int32_t>().swap(L.pg_count);
+    std::vector<uint8_t>().swap(L.pg_pts);
     if (p->mfma && d >= 3 && !L.tt_slot.empty()) {
       TargetTiles& TT = p->ttiles[d];
       int32_t *sl = nullptr, *tg = nullptr, *ee = nullptr;

@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   __shared__ T geo[NPTS][4];            // parent points about the parent centre, and r_p
   const int64_t q = xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15, gl = lane >> 4;
   for (int i = tid; i < NPTS * (W + 1); i += 256) (&acc[0][0])[i] = (T)0;
   const int32_t pb = P.slot_box[q];
@@ -282,32 +282,44 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   const T two_ds = (T)(2.0 * C.ns / kEtaD), two_da = (T)(2.0 * C.na / kPiD);
   T(*gb)[GW] = gbuf[wave];
   const int64_t t_beg = G.toff[q], t_end = G.toff[q + 1];
-  int64_t bg[4];
-  int bt[4];
-  // this wavefront owns tiles t_beg + wave + 4 i, taken four at a time
+  // this wavefront owns tiles t_beg + wave + 4 i, taken four at a time; the
+  // records of the next four are fetched while the current ones run
+  // rb / rn: the four records, wave-uniform; mine / mine_n: this lane's own
+  // record for the geometry phase (tile gl of the four)
+  int4 rb[4], rn[4], mine, mine_n;
+  int nb = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t tl = t_beg + wave + 4 * b;
+    rb[b] = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
+    nb += tl < t_end ? 1 : 0;
+  }
+  {
+    const int64_t tl = t_beg + wave + 4 * gl;
+    mine = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
+  }
   for (int64_t tb = t_beg + wave; tb < t_end; tb += 16) {
-    int nb = 0;
+    int nn = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int64_t tl = tb + 4 * b;
-      if (tl < t_end) {
-        bg[b] = G.tg[tl];
-        bt[b] = G.tt0[tl];
-        nb = b + 1;
-      }
+      const int64_t tl = tb + 16 + 4 * b;
+      rn[b] = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
+      nn += tl < t_end ? 1 : 0;
+    }
+    {
+      const int64_t tl = tb + 16 + 4 * gl;
+      mine_n = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
     }
     // geometry: lane -> (tile lane / 16, row lane % 16)
     {
       const int b = gl;
       if (b < nb) {
-        const int64_t gg = bg[b];
-        const int cnt = G.count[gg];
-        const int tt = bt[b];
-        const bool valid = tt + r16 < cnt;
-        const int p = valid ? (int)G.pts[G.start[gg] + tt + r16] : 0;
-        const int32_t slot = G.slot[gg];
-        const int cone = C.slot_cone[slot];
-        const double* cc = C.centers + 3 * G.cbox[gg];
+        const int4 rr = mine;
+        const int cnt = rr.w & 31;
+        const bool valid = r16 < cnt;
+        const int p = valid ? (int)G.pts[rr.z + r16] : 0;
+        const int cone = rr.w >> 5;
+        const double* cc = C.centers + 3 * (int64_t)rr.y;
         const T dx = (T)(cc[0] - cp[0]), dy = (T)(cc[1] - cp[1]), dz = (T)(cc[2] - cp[2]);
         const T Yx = geo[p][0], Yy = geo[p][1], Yz = geo[p][2], rp = geo[p][3];
         const T zx = Yx - dx, zy = Yy - dy, zz = Yz - dz;
@@ -351,12 +363,12 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int b = 0; b < nb; ++b) {
-      const int64_t gg = bg[b];
-      const int cnt = G.count[gg];
-      const int tt = bt[b];
-      const int64_t pstart = G.start[gg] + tt;
-      const T* Vs = Vc + (int64_t)G.slot[gg] * K * W + gl * W;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b >= nb) break;
+      const int cnt = rb[b].w & 31;
+      const int64_t pstart = rb[b].z;
+      const T* Vs = Vc + (int64_t)rb[b].x * K * W + gl * W;
       const T* me = gb[16 * b + r16];
       T Ls[PS], Lt[5];
 #pragma unroll
@@ -400,7 +412,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int orow = MF<T>::row(lane, e);
-        if (tt + orow < cnt) {
+        if (orow < cnt) {
           const int po = (int)G.pts[pstart + orow];
           const T fr = gb[16 * b + orow][16 + 2 * qq], fi = gb[16 * b + orow][17 + 2 * qq];
 #pragma unroll
@@ -413,6 +425,10 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       }
     }
     __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rb[b] = rn[b];
+    mine = mine_n;
+    nb = nn;
   }
   __syncthreads();
   T* out = Vp + q * (int64_t)K * W;

@@ -9,20 +9,14 @@
 
 namespace ifgf {
 
-// Propagation work list for one parent level: for parent cone slot q the
-// groups [off[q], off[q+1]); group g gathers the parent interpolation points
-// pts[start[g] .. start[g] + count[g]) that fall into child cone slot slot[g]
-// of child box cbox[g].
+// Propagation work list for one parent level: the tiles of parent cone slot
+// q are [toff[q], toff[q+1]); rec[t] = (child cone slot, child box, index of
+// the tile's first parent point in pts, child cone << 5 | points in the tile)
+// and pts holds the parent interpolation point numbers of the groups.
 struct PropGroups {
-  const int64_t* off = nullptr;
-  const int32_t* slot = nullptr;
-  const int32_t* cbox = nullptr;
-  const int64_t* start = nullptr;
-  const int32_t* count = nullptr;
+  const int64_t* toff = nullptr;
+  const int4* rec = nullptr;
   const uint8_t* pts = nullptr;
-  const int64_t* toff = nullptr;   // tiles of parent slot q: [toff[q], toff[q+1])
-  const int32_t* tg = nullptr;     // group of each tile
-  const uint8_t* tt0 = nullptr;    // first point (within the group) of each tile
 };
 
 // Target pairs of one level grouped by cone slot, in tiles of at most 8

@@ -176,6 +176,7 @@ void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts) {
   }
   Pl.pt_g.resize(Pl.pt_off[Q]);
   Pl.pt_t0.resize(Pl.pt_off[Q]);
+  Pl.pt_rec.resize(4 * Pl.pt_off[Q]);
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t q = 0; q < Q; ++q) {
     int64_t t = Pl.pt_off[q];
@@ -183,6 +184,11 @@ void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts) {
       for (int t0 = 0; t0 < Pl.pg_count[g]; t0 += 16, ++t) {
         Pl.pt_g[t] = (int32_t)g;
         Pl.pt_t0[t] = (uint8_t)t0;
+        int32_t* r = &Pl.pt_rec[4 * t];
+        r[0] = Pl.pg_slot[g];
+        r[1] = Pl.pg_cbox[g];
+        r[2] = (int32_t)(Pl.pg_start[g] + t0);
+        r[3] = (L.slot_cone[Pl.pg_slot[g]] << 5) | std::min(16, Pl.pg_count[g] - t0);
       }
   }
   (void)L;
@@ -462,7 +468,13 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
         }
       }
       if (bad2) { err = "internal: parent point outside relevant child cones"; return -1; }
-      if (npts <= 256) build_prop_groups(Pl, L, npts);
+      if (npts <= 256) {
+        if (Pl.pp_off[Pl.nslots] >= ((int64_t)1 << 31)) {
+          err = "too many propagation pairs on one level for the 32-bit tile records";
+          return -1;
+        }
+        build_prop_groups(Pl, L, npts);
+      }
     }
   }
 

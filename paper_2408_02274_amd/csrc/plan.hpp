@@ -50,6 +50,10 @@ struct HostLevel {
   std::vector<int64_t> pt_off;
   std::vector<int32_t> pt_g;
   std::vector<uint8_t> pt_t0;
+  // one record per tile, everything the propagation needs to start it:
+  // [tile][4] = child cone slot, child box, index of the tile's first point
+  // in pg_pts, child cone index << 5 | number of points (<= 16)
+  std::vector<int32_t> pt_rec;
   // the target pairs grouped by cone slot (targets ascending within a slot),
   // cut into tiles of at most 8 targets: tile t covers entries
   // [tt_start[t], tt_start[t] + tt_cnt[t]) of ts_tgt (sorted target) and
