@@ -310,7 +310,9 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       const int64_t tl = tb + 16 + 4 * gl;
       mine_n = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
     }
-    // geometry: lane -> (tile lane / 16, row lane % 16)
+    // geometry: lane -> (tile lane / 16, row lane % 16); the lane keeps its
+    // parent point index for the epilogues, which read it across lanes
+    int pme = 0;
     {
       const int b = gl;
       if (b < nb) {
@@ -318,6 +320,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         const int cnt = rr.w & 31;
         const bool valid = r16 < cnt;
         const int p = valid ? (int)G.pts[rr.z + r16] : 0;
+        pme = p;
         const int cone = rr.w >> 5;
         const double* cc = C.centers + 3 * (int64_t)rr.y;
         const T dx = (T)(cc[0] - cp[0]), dy = (T)(cc[1] - cp[1]), dz = (T)(cc[2] - cp[2]);
@@ -367,7 +370,6 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
     for (int b = 0; b < 4; ++b) {
       if (b >= nb) break;
       const int cnt = rb[b].w & 31;
-      const int64_t pstart = rb[b].z;
       const T* Vs = Vc + (int64_t)rb[b].x * K * W + gl * W;
       const T* me = gb[16 * b + r16];
       T Ls[PS], Lt[5];
@@ -412,8 +414,8 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int orow = MF<T>::row(lane, e);
+        const int po = __builtin_amdgcn_ds_bpermute((16 * b + orow) << 2, pme);
         if (orow < cnt) {
-          const int po = (int)G.pts[pstart + orow];
           const T fr = gb[16 * b + orow][16 + 2 * qq], fi = gb[16 * b + orow][17 + 2 * qq];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
