@@ -260,11 +260,13 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   __shared__ T acc[NPTS][W + 1];
   __shared__ T gbuf[4][64][GW];         // per wavefront: 4 tiles x 16 rows
   __shared__ T geo[NPTS][4];            // parent points about the parent centre, and r_p
+  __shared__ int acc_lock;              // held by the wavefront adding a tile into acc
   const int64_t q = xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15, gl = lane >> 4;
   for (int i = tid; i < NPTS * (W + 1); i += 256) (&acc[0][0])[i] = (T)0;
+  if (tid == 0) acc_lock = 0;
   const int32_t pb = P.slot_box[q];
   const int pcone = P.slot_cone[q];
   const double* cp = P.centers + 3 * pb;
@@ -411,17 +413,78 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       }
       // lane holds rows MF::row(lane, e), complex column r16 (kernel r16 / 8)
       const int qq = r16 >> 3;
+      if constexpr (sizeof(T) == 4) {
+        int po[4];
+        T zr[4][R], zi[4][R];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int orow = MF<T>::row(lane, e);
-        const int po = __builtin_amdgcn_ds_bpermute((16 * b + orow) << 2, pme);
-        if (orow < cnt) {
-          const T fr = gb[16 * b + orow][16 + 2 * qq], fi = gb[16 * b + orow][17 + 2 * qq];
+        for (int e = 0; e < 4; ++e) {
+          const int orow = MF<T>::row(lane, e);
+          po[e] = __builtin_amdgcn_ds_bpermute((16 * b + orow) << 2, pme);
+          const int ro = orow < cnt ? orow : 0;
+          const T fr = gb[16 * b + ro][16 + 2 * qq], fi = gb[16 * b + ro][17 + 2 * qq];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const T vr = c0[r][e], vi = c1[r][e];
-            atomicAdd(&acc[po][32 * r + r16], fr * vr - fi * vi);
-            atomicAdd(&acc[po][32 * r + 16 + r16], fr * vi + fi * vr);
+            zr[e][r] = fr * vr - fi * vi;
+            zi[e][r] = fr * vi + fi * vr;
+          }
+        }
+        // The rows of one tile are distinct parent points, so the tile is added
+        // with plain loads and stores; other wavefronts of the block add tiles
+        // of other child boxes into the same points, hence the block lock
+        // around the read-add-write (cheaper than per-element LDS atomics).
+        if (lane == 0) {
+          int expected = 0;
+#pragma unroll 1
+          for (int spin = 0; spin < (1 << 22); ++spin) {   // bounded: the wait always ends
+            if (__hip_atomic_compare_exchange_strong(&acc_lock, &expected, 1, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
+              break;
+            expected = 0;
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        T oldr[4][R], oldi[4][R];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (MF<T>::row(lane, e) < cnt) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              oldr[e][r] = acc[po[e]][32 * r + r16];
+              oldi[e][r] = acc[po[e]][32 * r + 16 + r16];
+            }
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (MF<T>::row(lane, e) < cnt) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              acc[po[e]][32 * r + r16] = oldr[e][r] + zr[e][r];
+              acc[po[e]][32 * r + 16 + r16] = oldi[e][r] + zi[e][r];
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) __hip_atomic_store(&acc_lock, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        // FP64: native LDS add of doubles, no lock (the extra registers of
+        // the locked form would halve the occupancy of this kernel)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int orow = MF<T>::row(lane, e);
+          const int pe = __builtin_amdgcn_ds_bpermute((16 * b + orow) << 2, pme);
+          if (orow < cnt) {
+            const T fr = gb[16 * b + orow][16 + 2 * qq], fi = gb[16 * b + orow][17 + 2 * qq];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const T vr = c0[r][e], vi = c1[r][e];
+              atomicAdd(&acc[pe][32 * r + r16], fr * vr - fi * vi);
+              atomicAdd(&acc[pe][32 * r + 16 + r16], fr * vi + fi * vr);
+            }
           }
         }
       }
