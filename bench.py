@@ -112,8 +112,9 @@ def cpu_baseline(surface, ks, w, sample_rows, seed=2):
 def batching(log, reps=5):
     """64 random right-hand sides on the unit sphere (24 patches x 8 x 8
     nodes, k_ext = 2 pi, eps_r 2.25): one-at-a-time applies, one batched
-    apply (column batch chosen by the autotuner), and one graph launch of the
-    batched apply."""
+    apply (column batch chosen by the autotuner), one graph launch of the
+    batched apply, and GMRES for 64 plane waves in lock-step vs one at a
+    time."""
     import torch
     import synth
     from paper_2408_02274_amd import NMullerGraph, NMullerOperator
@@ -142,6 +143,29 @@ def batching(log, reps=5):
            "rhs_matvecs_per_s_graph": 64 / t_graph, "graph_nodes": g.nodes, "autotuned_columns": cols,
            "ms_looped": t_loop * 1e3, "ms_batched": t_batch * 1e3, "ms_graph": t_graph * 1e3}
     g.close()
+    # GMRES for 64 plane waves (directions uniform on the sphere, polarisations
+    # uniform in the tangent plane): lock-step batch vs one solve at a time
+    import numpy as np
+    d, pol = synth.plane_wave_batch(64, 3)
+    ke = 2 * math.pi
+    ph = np.exp(1j * ke * (s.x @ d.T)).T                   # [64][n]
+    E = pol[:, None, :] * ph[:, :, None]
+    H = np.cross(d, pol)[:, None, :] * ph[:, :, None]
+    b = op.rhs(torch.from_numpy(E).to("cuda"), torch.from_numpy(H).to("cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = op.solve(b, rtol=1e-4, maxit=300)
+    torch.cuda.synchronize()
+    t_lock = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lone = [op.solve(b[r:r + 1].contiguous(), rtol=1e-4, maxit=300)[1][0] for r in range(64)]
+    torch.cuda.synchronize()
+    t_lone = time.perf_counter() - t0
+    res["gmres_64_plane_waves"] = {
+        "rtol": 1e-4, "lockstep_seconds": t_lock, "one_at_a_time_seconds": t_lone,
+        "iterations_total": sum(i["iters"] for i in info), "iterations_max": max(i["iters"] for i in info),
+        "all_converged": all(i["converged"] for i in info) and all(i["converged"] for i in lone),
+        "lockstep_speedup": t_lone / t_lock}
     op.close()
     log(f"batching: {res}")
     return res

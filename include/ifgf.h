@@ -210,7 +210,8 @@ typedef struct {
   int converged;          /* 1 when true_relres <= rtol                        */
   double true_relres;     /* ||b - A y|| / ||b|| from a final FP64 matvec      */
   double arnoldi_relres;  /* GMRES residual estimate at exit                   */
-  double seconds;         /* host wall time of this right-hand side            */
+  double seconds;         /* host wall time from the start of its lock-step
+                             group until this right-hand side finished        */
   int precond_iters;      /* iterations run with the network part of M on      */
   int fallbacks;          /* preconditioned cycles abandoned (see below)       */
 } ifgf_solve_info;
@@ -222,8 +223,16 @@ typedef struct {
  *  rhs  device [nrhs][4][n] complex FP64
  *  y    device [nrhs][4][n]: initial guess if use_x0, else overwritten from 0
  *  info host [nrhs] (may be NULL)
+ * Several right-hand sides run in lock-step (project addition): each step
+ * gathers the pending products of all unconverged solves into batched
+ * applies of up to max_nrhs columns (the operator's creation option);
+ * converged solves drop out.  The group holds as many solves as half the
+ * free device memory allows for their Krylov bases (16 B x 4n x (basis + 1,
+ * plus basis with a preconditioner)); larger nrhs run group after group.
+ * Each solve's arithmetic is that of a lone solve.
  * Returns IFGF_WNOCONV (> 0) if some true residual exceeds rtol; the best
- * iterate is still returned.  Synchronises the stream once per iteration.  */
+ * iterate is still returned.  Synchronises the stream a few times per
+ * iteration and right-hand side.                                            */
 int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, int use_x0, double rtol,
                   int maxit, int restart, ifgf_solve_info* info, void* stream);
 

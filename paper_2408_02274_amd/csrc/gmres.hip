@@ -17,7 +17,9 @@
 
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <complex>
+#include <memory>
 #include <vector>
 
 #include "../../include/ifgf.h"
@@ -198,148 +200,281 @@ struct Recorder {
 
 bool finite(cd a) { return std::isfinite(a.real()) && std::isfinite(a.imag()); }
 
-// One right-hand side.  Returns a status code; fills `inf`.
-int solve_one(Solver& S, const double2* b, double2* x, double rtol, int maxit, bool precond, Recorder* rec,
-              bool fp64_residual, ifgf_solve_info& inf) {
-  auto t0 = std::chrono::steady_clock::now();
-  ifgf::Precond* pc = precond ? nmuller_precond(S.nm) : nullptr;
-  bool net = pc != nullptr;   // network part of M in use
-  const int basis = S.basis;
-  std::vector<cd> H((size_t)(basis + 1) * basis), cs(basis), sn(basis), g(basis + 1), hv(basis + 2);
-  std::vector<double> hist;
-  double bnorm = 0.0;
-  int rc;
-  if ((rc = S.norm(b, &bnorm))) return rc;
-  int total = 0, pc_iters = 0, fallbacks = 0;
-  double est = 0.0, truerel = 0.0;
-  if (bnorm == 0.0) hipLaunchKernelGGL(k_fill, dim3(nblk(S.m)), dim3(kBS), 0, S.st, x, S.m);
-  // Each cycle starts from the true FP64 residual, which alone decides
-  // convergence; the Arnoldi process may run on the FP32 operator.
-  while (bnorm > 0.0) {
-    if ((rc = S.residual(b, x, fp64_residual))) return rc;
-    double beta = 0.0;
-    if ((rc = S.norm(S.tmp, &beta))) return rc;
-    truerel = beta / bnorm;
-    est = truerel;
-    if (truerel <= rtol || total >= maxit) break;
-    hipLaunchKernelGGL(k_axpy, dim3(nblk(S.m)), dim3(kBS), 0, S.st, make_double2(1.0 / beta, 0.0), S.tmp,
-                       (const double2*)nullptr, S.V, S.m);
-    std::fill(g.begin(), g.end(), cd(0.0));
-    g[0] = beta;
-    hist.assign(1, truerel);
-    const bool flex = pc != nullptr;
-    bool abandon = false;
-    int k = 0;   // columns accepted in this cycle
-    while (k < basis && total < maxit) {
-      double2* Vk = S.V + (int64_t)k * S.m;
-      const double2* src = Vk;
-      if (flex) {
-        double2* Zk = S.Z + (int64_t)k * S.m;
-        hipError_t e = ifgf::precond_apply(*pc, Vk, Zk, S.st, net);
-        if (e != hipSuccess) return set_hip_error(e, "preconditioner");
-        src = Zk;
-      }
-      if ((rc = nmuller_apply(S.nm, src, 1, S.w, S.st))) return rc;
-      for (int pass = 0; pass < 2; ++pass) {   // CGS2
-        hipError_t e = S.dots(S.V, k + 1, S.w, S.h);
-        if (e != hipSuccess) return set_hip_error(e, "gmres dots");
-        hipLaunchKernelGGL(k_orth_update, dim3(nblk(S.m)), dim3(kBS), 0, S.st, S.V, S.m, S.h, k + 1, S.w, S.m);
-        std::vector<double2> hh(k + 1);
-        if ((e = hipMemcpyAsync(hh.data(), S.h, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, S.st)) !=
-                hipSuccess ||
-            (e = hipStreamSynchronize(S.st)) != hipSuccess)
-          return set_hip_error(e, "gmres copy");
-        for (int j = 0; j <= k; ++j) {
-          cd v(hh[j].x, hh[j].y);
-          hv[j] = pass ? hv[j] + v : v;
-        }
-      }
-      double hn = 0.0;
-      if ((rc = S.norm(S.w, &hn))) return rc;
-      bool ok = std::isfinite(hn);
-      for (int j = 0; j <= k && ok; ++j) ok = finite(hv[j]);
-      if (!ok) {
-        if (flex && net) {   // discard this column and switch the network off
-          abandon = true;
-          break;
-        }
-        return set_error(IFGF_EINVAL, "non-finite vector in the Arnoldi process");
-      }
-      for (int j = 0; j <= k; ++j) H[(size_t)j * basis + k] = hv[j];
-      H[(size_t)(k + 1) * basis + k] = hn;
-      for (int i = 0; i < k; ++i) {
-        cd a = H[(size_t)i * basis + k], bb = H[(size_t)(i + 1) * basis + k];
-        H[(size_t)i * basis + k] = std::conj(cs[i]) * a + std::conj(sn[i]) * bb;
-        H[(size_t)(i + 1) * basis + k] = -sn[i] * a + cs[i] * bb;
-      }
-      cd a = H[(size_t)k * basis + k], bb = H[(size_t)(k + 1) * basis + k];
-      double den = std::sqrt(std::norm(a) + std::norm(bb));
-      cs[k] = den > 0 ? a / den : cd(1.0);
-      sn[k] = den > 0 ? bb / den : cd(0.0);
-      H[(size_t)k * basis + k] = den;
-      H[(size_t)(k + 1) * basis + k] = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = std::conj(cs[k]) * g[k];
-      est = std::abs(g[k + 1]) / bnorm;
-      if (hn > 0.0)
-        hipLaunchKernelGGL(k_axpy, dim3(nblk(S.m)), dim3(kBS), 0, S.st, make_double2(1.0 / hn, 0.0), S.w,
-                           (const double2*)nullptr, S.V + (int64_t)(k + 1) * S.m, S.m);
-      ++k;
-      ++total;
-      if (flex && net) ++pc_iters;
-      hist.push_back(est);
-      if (rec && rec->count < rec->cap && total % rec->stride == 0) {
-        // iterate x + B y and its residual V_{k+1} Q^H (0, .., 0, g_k)
-        std::vector<cd> yy(k), u(k + 1, cd(0.0));
-        for (int i = k - 1; i >= 0; --i) {
-          cd s = g[i];
-          for (int j = i + 1; j < k; ++j) s -= H[(size_t)i * basis + j] * yy[j];
-          yy[i] = s / H[(size_t)i * basis + i];
-        }
-        u[k] = g[k];
-        for (int i = k - 1; i >= 0; --i) {
-          cd ui = u[i], ui1 = u[i + 1];
-          u[i] = cs[i] * ui - std::conj(sn[i]) * ui1;
-          u[i + 1] = sn[i] * ui + std::conj(cs[i]) * ui1;
-        }
-        double2* Xr = rec->X + (int64_t)rec->count * S.m;
-        double2* Rr = rec->R + (int64_t)rec->count * S.m;
-        hipLaunchKernelGGL(k_axpy, dim3(nblk(S.m)), dim3(kBS), 0, S.st, make_double2(1.0, 0.0), x,
-                           (const double2*)nullptr, Xr, S.m);
-        if ((rc = S.combine(flex ? S.Z : S.V, yy, k, Xr, false)) || (rc = S.combine(S.V, u, k + 1, Rr, true)))
-          return rc;
-        rec->count += 1;
-      }
-      if (est <= rtol || hn == 0.0) break;
-      if (flex && net && k >= kStallWindow && !(est < kStallRatio * hist[k - kStallWindow])) {
-        abandon = true;
-        break;
-      }
-    }
-    if (k > 0) {
-      // x += B y with H y = g (upper triangular)
-      std::vector<cd> yy(k);
-      for (int i = k - 1; i >= 0; --i) {
-        cd s = g[i];
-        for (int j = i + 1; j < k; ++j) s -= H[(size_t)i * basis + j] * yy[j];
-        yy[i] = s / H[(size_t)i * basis + i];
-      }
-      if ((rc = S.combine(flex ? S.Z : S.V, yy, k, x, false))) return rc;
-    }
-    if (abandon) {
-      net = false;
-      ++fallbacks;
-    }
+// The operator product a solve needs next: dst = A src, with the FP64 form
+// of the operator (true residuals) or its working form (Arnoldi).
+struct Req {
+  const double2* src = nullptr;
+  double2* dst = nullptr;
+  bool fp64 = false;
+};
+
+// One right-hand side as a resumable FGMRES: start() and resume() run the
+// solve up to its next operator product and return that product as a
+// request; the caller performs it (alone or batched with other solves) and
+// calls resume().  Every step of the algorithm lives here, so a lone solve
+// and a lock-step batch of solves run the same arithmetic.
+class Fgmres {
+ public:
+  Fgmres(Solver& S, const double2* b, double2* x, double rtol, int maxit, bool precond, Recorder* rec,
+         bool fp64_residual)
+      : S_(S), b_(b), x_(x), rtol_(rtol), maxit_(maxit), rec_(rec), fp64_res_(fp64_residual),
+        basis_(S.basis), H_((size_t)(S.basis + 1) * S.basis), cs_(S.basis), sn_(S.basis), g_(S.basis + 1),
+        hv_(S.basis + 2) {
+    pc_ = precond ? nmuller_precond(S.nm) : nullptr;
+    net_ = pc_ != nullptr;
   }
-  auto t1 = std::chrono::steady_clock::now();
-  inf.iters = total;
-  inf.true_relres = truerel;
-  inf.arnoldi_relres = est;
-  inf.converged = truerel <= rtol ? 1 : 0;
-  inf.seconds = std::chrono::duration<double>(t1 - t0).count();
-  inf.precond_iters = pc_iters;
-  inf.fallbacks = fallbacks;
-  return 0;
+
+  int start(Req* req, bool* done) {
+    t0_ = std::chrono::steady_clock::now();
+    int rc;
+    if ((rc = S_.norm(b_, &bnorm_))) return rc;
+    if (bnorm_ == 0.0) {
+      hipLaunchKernelGGL(k_fill, dim3(nblk(S_.m)), dim3(kBS), 0, S_.st, x_, S_.m);
+      return finish(done);
+    }
+    return request_residual(req, done);
+  }
+
+  int resume(Req* req, bool* done) {
+    return phase_ == kResidual ? after_residual(req, done) : after_arnoldi(req, done);
+  }
+
+  const ifgf_solve_info& info() const { return inf_; }
+
+ private:
+  enum Phase { kResidual, kArnoldi };
+
+  // Each cycle starts from the true residual tmp = b - A x (FP64 form when
+  // fp64_res_), which alone decides convergence; the Arnoldi process may run
+  // on the FP32 operator.
+  int request_residual(Req* req, bool* done) {
+    phase_ = kResidual;
+    *req = Req{x_, S_.tmp, fp64_res_};
+    *done = false;
+    return 0;
+  }
+
+  int after_residual(Req* req, bool* done) {
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(S_.m)), dim3(kBS), 0, S_.st, make_double2(-1.0, 0.0), S_.tmp, b_,
+                       S_.tmp, S_.m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "gmres residual");
+    double beta = 0.0;
+    int rc;
+    if ((rc = S_.norm(S_.tmp, &beta))) return rc;
+    truerel_ = beta / bnorm_;
+    est_ = truerel_;
+    if (truerel_ <= rtol_ || total_ >= maxit_) return finish(done);
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(S_.m)), dim3(kBS), 0, S_.st, make_double2(1.0 / beta, 0.0), S_.tmp,
+                       (const double2*)nullptr, S_.V, S_.m);
+    std::fill(g_.begin(), g_.end(), cd(0.0));
+    g_[0] = beta;
+    hist_.assign(1, truerel_);
+    flex_ = pc_ != nullptr;
+    abandon_ = false;
+    k_ = 0;
+    return request_column(req, done);
+  }
+
+  // column k of the cycle: z_k = M(v_k) when flexible, then w = A z_k
+  int request_column(Req* req, bool* done) {
+    double2* Vk = S_.V + (int64_t)k_ * S_.m;
+    const double2* src = Vk;
+    if (flex_) {
+      double2* Zk = S_.Z + (int64_t)k_ * S_.m;
+      hipError_t e = ifgf::precond_apply(*pc_, Vk, Zk, S_.st, net_);
+      if (e != hipSuccess) return set_hip_error(e, "preconditioner");
+      src = Zk;
+    }
+    phase_ = kArnoldi;
+    *req = Req{src, S_.w, false};
+    *done = false;
+    return 0;
+  }
+
+  int after_arnoldi(Req* req, bool* done) {
+    const int k = k_;
+    int rc;
+    for (int pass = 0; pass < 2; ++pass) {   // CGS2
+      hipError_t e = S_.dots(S_.V, k + 1, S_.w, S_.h);
+      if (e != hipSuccess) return set_hip_error(e, "gmres dots");
+      hipLaunchKernelGGL(k_orth_update, dim3(nblk(S_.m)), dim3(kBS), 0, S_.st, S_.V, S_.m, S_.h, k + 1, S_.w,
+                         S_.m);
+      std::vector<double2> hh(k + 1);
+      if ((e = hipMemcpyAsync(hh.data(), S_.h, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, S_.st)) !=
+              hipSuccess ||
+          (e = hipStreamSynchronize(S_.st)) != hipSuccess)
+        return set_hip_error(e, "gmres copy");
+      for (int j = 0; j <= k; ++j) {
+        cd v(hh[j].x, hh[j].y);
+        hv_[j] = pass ? hv_[j] + v : v;
+      }
+    }
+    double hn = 0.0;
+    if ((rc = S_.norm(S_.w, &hn))) return rc;
+    bool ok = std::isfinite(hn);
+    for (int j = 0; j <= k && ok; ++j) ok = finite(hv_[j]);
+    if (!ok) {
+      if (flex_ && net_) {   // discard this column and switch the network off
+        abandon_ = true;
+        return end_cycle(req, done);
+      }
+      return set_error(IFGF_EINVAL, "non-finite vector in the Arnoldi process");
+    }
+    const int basis = basis_;
+    for (int j = 0; j <= k; ++j) H_[(size_t)j * basis + k] = hv_[j];
+    H_[(size_t)(k + 1) * basis + k] = hn;
+    for (int i = 0; i < k; ++i) {
+      cd a = H_[(size_t)i * basis + k], bb = H_[(size_t)(i + 1) * basis + k];
+      H_[(size_t)i * basis + k] = std::conj(cs_[i]) * a + std::conj(sn_[i]) * bb;
+      H_[(size_t)(i + 1) * basis + k] = -sn_[i] * a + cs_[i] * bb;
+    }
+    cd a = H_[(size_t)k * basis + k], bb = H_[(size_t)(k + 1) * basis + k];
+    double den = std::sqrt(std::norm(a) + std::norm(bb));
+    cs_[k] = den > 0 ? a / den : cd(1.0);
+    sn_[k] = den > 0 ? bb / den : cd(0.0);
+    H_[(size_t)k * basis + k] = den;
+    H_[(size_t)(k + 1) * basis + k] = 0.0;
+    g_[k + 1] = -sn_[k] * g_[k];
+    g_[k] = std::conj(cs_[k]) * g_[k];
+    est_ = std::abs(g_[k + 1]) / bnorm_;
+    if (hn > 0.0)
+      hipLaunchKernelGGL(k_axpy, dim3(nblk(S_.m)), dim3(kBS), 0, S_.st, make_double2(1.0 / hn, 0.0), S_.w,
+                         (const double2*)nullptr, S_.V + (int64_t)(k + 1) * S_.m, S_.m);
+    k_ = k + 1;
+    ++total_;
+    if (flex_ && net_) ++pc_iters_;
+    hist_.push_back(est_);
+    if (rec_ && rec_->count < rec_->cap && total_ % rec_->stride == 0 && (rc = record())) return rc;
+    if (est_ <= rtol_ || hn == 0.0) return end_cycle(req, done);
+    if (flex_ && net_ && k_ >= kStallWindow && !(est_ < kStallRatio * hist_[k_ - kStallWindow])) {
+      abandon_ = true;
+      return end_cycle(req, done);
+    }
+    if (k_ < basis_ && total_ < maxit_) return request_column(req, done);
+    return end_cycle(req, done);
+  }
+
+  // y solving H y = g (upper triangular, first nk rows)
+  std::vector<cd> hess_solve(int nk) const {
+    std::vector<cd> yy(nk);
+    for (int i = nk - 1; i >= 0; --i) {
+      cd s = g_[i];
+      for (int j = i + 1; j < nk; ++j) s -= H_[(size_t)i * basis_ + j] * yy[j];
+      yy[i] = s / H_[(size_t)i * basis_ + i];
+    }
+    return yy;
+  }
+
+  // iterate x + B y and its residual V_{k+1} Q^H (0, .., 0, g_k)
+  int record() {
+    const int k = k_;
+    std::vector<cd> yy = hess_solve(k), u(k + 1, cd(0.0));
+    u[k] = g_[k];
+    for (int i = k - 1; i >= 0; --i) {
+      cd ui = u[i], ui1 = u[i + 1];
+      u[i] = cs_[i] * ui - std::conj(sn_[i]) * ui1;
+      u[i + 1] = sn_[i] * ui + std::conj(cs_[i]) * ui1;
+    }
+    double2* Xr = rec_->X + (int64_t)rec_->count * S_.m;
+    double2* Rr = rec_->R + (int64_t)rec_->count * S_.m;
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(S_.m)), dim3(kBS), 0, S_.st, make_double2(1.0, 0.0), x_,
+                       (const double2*)nullptr, Xr, S_.m);
+    int rc;
+    if ((rc = S_.combine(flex_ ? S_.Z : S_.V, yy, k, Xr, false)) || (rc = S_.combine(S_.V, u, k + 1, Rr, true)))
+      return rc;
+    rec_->count += 1;
+    return 0;
+  }
+
+  // x += B y; a cycle abandoned by the network goes on with M = D^-1
+  int end_cycle(Req* req, bool* done) {
+    int rc;
+    if (k_ > 0 && (rc = S_.combine(flex_ ? S_.Z : S_.V, hess_solve(k_), k_, x_, false))) return rc;
+    if (abandon_) {
+      net_ = false;
+      ++fallbacks_;
+    }
+    return request_residual(req, done);
+  }
+
+  int finish(bool* done) {
+    auto t1 = std::chrono::steady_clock::now();
+    inf_.iters = total_;
+    inf_.true_relres = truerel_;
+    inf_.arnoldi_relres = est_;
+    inf_.converged = truerel_ <= rtol_ ? 1 : 0;
+    inf_.seconds = std::chrono::duration<double>(t1 - t0_).count();
+    inf_.precond_iters = pc_iters_;
+    inf_.fallbacks = fallbacks_;
+    *done = true;
+    return 0;
+  }
+
+  Solver& S_;
+  const double2* b_;
+  double2* x_;
+  double rtol_;
+  int maxit_;
+  Recorder* rec_;
+  bool fp64_res_;
+  ifgf::Precond* pc_ = nullptr;
+  bool net_ = false;   // network part of M in use
+  int basis_;
+  std::vector<cd> H_, cs_, sn_, g_, hv_;
+  std::vector<double> hist_;
+  double bnorm_ = 0.0, est_ = 0.0, truerel_ = 0.0;
+  int total_ = 0, pc_iters_ = 0, fallbacks_ = 0, k_ = 0;
+  bool flex_ = false, abandon_ = false;
+  Phase phase_ = kResidual;
+  std::chrono::steady_clock::time_point t0_;
+  ifgf_solve_info inf_{};
+};
+
+// Perform the requests rs (all of one precision) as batched operator
+// products: up to `cap` sources packed into P, one apply, results unpacked
+// from Q.  A lone request is applied in place.
+int apply_requests(nmuller_t nm, const std::vector<Req*>& rs, bool fp64, int cap, double2* P, double2* Q,
+                   int64_t m, hipStream_t st) {
+  if (rs.empty()) return 0;
+  ifgf_plan_t ip = nmuller_ifgf(nm);
+  int prev = IFGF_FP64;
+  int rc = fp64 ? ifgf_set_precision(ip, IFGF_FP64, &prev) : 0;
+  if (rc) return rc;
+  const size_t vb = sizeof(double2) * (size_t)m;
+  for (size_t c0 = 0; c0 < rs.size() && !rc; c0 += cap) {
+    const int nb = (int)std::min<size_t>(cap, rs.size() - c0);
+    if (nb == 1) {
+      rc = nmuller_apply(nm, rs[c0]->src, 1, rs[c0]->dst, st);
+      continue;
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nb && e == hipSuccess; ++i)
+      e = hipMemcpyAsync(P + (int64_t)i * m, rs[c0 + i]->src, vb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+      rc = set_hip_error(e, "gmres pack");
+      break;
+    }
+    if ((rc = nmuller_apply(nm, P, nb, Q, st))) break;
+    for (int i = 0; i < nb && e == hipSuccess; ++i)
+      e = hipMemcpyAsync(rs[c0 + i]->dst, Q + (int64_t)i * m, vb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) rc = set_hip_error(e, "gmres unpack");
+  }
+  int rc2 = fp64 ? ifgf_set_precision(ip, prev, nullptr) : 0;
+  return rc ? rc : rc2;
+}
+
+// A single solve driven to the end.
+int run_one(Fgmres& G, nmuller_t nm, int64_t m, hipStream_t st) {
+  Req r;
+  bool done = false;
+  int rc = G.start(&r, &done);
+  while (!rc && !done) {
+    std::vector<Req*> one{&r};
+    if ((rc = apply_requests(nm, one, r.fp64, 1, nullptr, nullptr, m, st))) break;
+    rc = G.resume(&r, &done);
+  }
+  return rc;
 }
 
 int solver_size(nmuller_t nm, int64_t* n) {
@@ -362,20 +497,76 @@ extern "C" int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, i
   int rc = solver_size(nm, &n);
   if (rc) return rc;
   const bool precond = nmuller_precond(nm) != nullptr;
-  Solver S;
-  S.nm = nm;
-  S.m = 4 * n;
-  S.st = static_cast<hipStream_t>(stream);
-  if ((rc = S.init((restart > 0 && restart < maxit) ? restart : maxit, precond))) return rc;
+  const int64_t m = 4 * n;
+  const int basis = (restart > 0 && restart < maxit) ? restart : maxit;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // Right-hand sides advance in lock-step groups: each step gathers the
+  // pending operator products of the group's unconverged solves into
+  // batched applies (converged solves drop out).  A group is as large as
+  // half the free device memory allows for the solves' Krylov bases.
+  const double per_solve = 16.0 * (double)m * ((basis + 1) + (precond ? basis : 0) + 2);
+  size_t free_b = 0, total_b = 0;
+  hipError_t e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return set_hip_error(e, "gmres memory query");
+  const int cap = nmuller_max_rhs(nm);
+  int group = (int)std::min<double>(nrhs, std::max(1.0, std::floor(0.5 * (double)free_b / per_solve)));
   int status = IFGF_OK;
-  for (int r = 0; r < nrhs; ++r) {
-    const double2* b = static_cast<const double2*>(rhs) + (int64_t)r * S.m;
-    double2* x = static_cast<double2*>(y) + (int64_t)r * S.m;
-    if (!use_x0) hipLaunchKernelGGL(k_fill, dim3(nblk(S.m)), dim3(kBS), 0, S.st, x, S.m);
-    ifgf_solve_info inf{};
-    if ((rc = solve_one(S, b, x, rtol, maxit, precond, nullptr, true, inf))) return rc;
-    if (info) info[r] = inf;
-    if (!inf.converged) status = IFGF_WNOCONV;
+  for (int r0 = 0; r0 < nrhs; r0 += group) {
+    const int gn = std::min(group, nrhs - r0);
+    std::vector<std::unique_ptr<Solver>> Ss(gn);
+    std::vector<std::unique_ptr<Fgmres>> Gs(gn);
+    for (int i = 0; i < gn; ++i) {
+      Ss[i] = std::make_unique<Solver>();
+      Ss[i]->nm = nm;
+      Ss[i]->m = m;
+      Ss[i]->st = st;
+      if ((rc = Ss[i]->init(basis, precond))) return rc;
+      const double2* b = static_cast<const double2*>(rhs) + (int64_t)(r0 + i) * m;
+      double2* x = static_cast<double2*>(y) + (int64_t)(r0 + i) * m;
+      if (!use_x0) hipLaunchKernelGGL(k_fill, dim3(nblk(m)), dim3(kBS), 0, st, x, m);
+      Gs[i] = std::make_unique<Fgmres>(*Ss[i], b, x, rtol, maxit, precond, nullptr, true);
+    }
+    if (gn == 1) {
+      if ((rc = run_one(*Gs[0], nm, m, st))) return rc;
+    } else {
+      DeviceArena pack;
+      const int nb = std::min(cap, gn);
+      double2 *P = nullptr, *Q = nullptr;
+      if (nb > 1) {
+        P = static_cast<double2*>(pack.alloc(sizeof(double2) * (size_t)m * nb));
+        Q = static_cast<double2*>(pack.alloc(sizeof(double2) * (size_t)m * nb));
+        if (!P || !Q) return set_error(IFGF_ENOMEM, "GMRES batch buffers");
+      }
+      std::vector<Req> reqs(gn);
+      std::vector<char> done(gn, 0);
+      for (int i = 0; i < gn; ++i) {
+        bool d = false;
+        if ((rc = Gs[i]->start(&reqs[i], &d))) return rc;
+        done[i] = d;
+      }
+      for (;;) {
+        std::vector<Req*> r64, rwk;
+        std::vector<int> act;
+        for (int i = 0; i < gn; ++i)
+          if (!done[i]) {
+            act.push_back(i);
+            (reqs[i].fp64 ? r64 : rwk).push_back(&reqs[i]);
+          }
+        if (act.empty()) break;
+        if ((rc = apply_requests(nm, r64, true, cap, P, Q, m, st)) ||
+            (rc = apply_requests(nm, rwk, false, cap, P, Q, m, st)))
+          return rc;
+        for (int i : act) {
+          bool d = false;
+          if ((rc = Gs[i]->resume(&reqs[i], &d))) return rc;
+          done[i] = d;
+        }
+      }
+    }
+    for (int i = 0; i < gn; ++i) {
+      if (info) info[r0 + i] = Gs[i]->info();
+      if (!Gs[i]->info().converged) status = IFGF_WNOCONV;
+    }
   }
   return status;
 }
@@ -402,9 +593,9 @@ extern "C" int nmuller_solve_trajectory(nmuller_t nm, const void* rhs, void* y, 
   rec.R = static_cast<double2*>(R);
   rec.cap = cap;
   rec.stride = stride;
-  ifgf_solve_info inf{};
-  if ((rc = solve_one(S, static_cast<const double2*>(rhs), x, rtol, maxit, false, &rec, false, inf))) return rc;
+  Fgmres G(S, static_cast<const double2*>(rhs), x, rtol, maxit, false, &rec, false);
+  if ((rc = run_one(G, nm, S.m, S.st))) return rc;
   *nrec = rec.count;
-  if (info) *info = inf;
-  return inf.converged ? IFGF_OK : IFGF_WNOCONV;
+  if (info) *info = G.info();
+  return G.info().converged ? IFGF_OK : IFGF_WNOCONV;
 }

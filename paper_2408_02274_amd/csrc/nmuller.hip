@@ -278,6 +278,7 @@ struct nmuller_s {
 };
 
 ifgf::Precond* nmuller_precond(nmuller_s* nm) { return nm ? nm->pc.get() : nullptr; }
+int nmuller_max_rhs(nmuller_s* nm) { return nm ? nm->max_nrhs : 1; }
 
 namespace {
 template <class T>

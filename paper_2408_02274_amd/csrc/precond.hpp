@@ -56,3 +56,5 @@ hipError_t precond_pairs(Precond& pc, const double2* R, const double2* E, int np
 
 struct nmuller_s;
 ifgf::Precond* nmuller_precond(nmuller_s* nm);
+// right-hand sides one nmuller_apply may take (the operator's max_nrhs)
+int nmuller_max_rhs(nmuller_s* nm);

@@ -124,3 +124,54 @@ def test_autotune_picks_a_valid_column_batch():
     one = p.apply(d[5:6].contiguous())
     assert _rel(out[5], one[0]) < 1e-6
     p.close()
+
+
+def _plane_waves(nm_o, nrhs, seed):
+    """Config-3a incidences: d ~ normalise(N(0, I)), p = cos(psi) e1 + sin(psi) e2."""
+    rng = np.random.default_rng(seed)
+    Es, Hs = [], []
+    for _ in range(nrhs):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        a = np.array([1.0, 0, 0]) if abs(d[0]) < 0.9 else np.array([0, 1.0, 0])
+        e1 = np.cross(d, a)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(d, e1)
+        psi = rng.uniform(0, 2 * math.pi)
+        E, H = nm_o.incident_plane_wave(d, math.cos(psi) * e1 + math.sin(psi) * e2)
+        Es.append(E)
+        Hs.append(H)
+    return np.stack(Es), np.stack(Hs)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lockstep_solve_equals_lone_solves(prec):
+    """Six right-hand sides (one of them zero) solved in lock-step with
+    batched applies of up to 4 columns equal six lone solves: same iteration
+    counts, same solutions up to the accumulation-order rounding of the
+    operator."""
+    from oracle import nmuller, surface
+    from paper_2408_02274_amd import NMullerOperator
+    from paper_2408_02274_amd import binding as B
+    s = synth.cube_sphere(2, 8, 1.0)
+    surf = surface.PatchSurface(s.P, s.nc, s.x, s.du, s.dv)
+    nm_o = nmuller.NMuller(surf, 1.0, 2.25, corrections={})
+    E, H = _plane_waves(nm_o, 6, 3)
+    p = B.IFGF_FP64 if prec == "fp64" else B.IFGF_FP32
+    _say(f"[gpu] lock-step GMRES {prec}, 6 RHS, batches of 4")
+    op = NMullerOperator(s, 1.0, 2.25, tol=1e-3, Ps=5, Pa=5, precision=p, max_nrhs=4)
+    b = op.rhs(torch.from_numpy(E).to("cuda"), torch.from_numpy(H).to("cuda"))
+    b[2].zero_()
+    # the FP32 form's true (FP64) residual bottoms out near its 1e-5 error
+    rtol = 1e-6 if prec == "fp64" else 1e-4
+    y, info = op.solve(b, rtol=rtol, maxit=200, restart=12)
+    assert info[2]["converged"] and info[2]["iters"] == 0 and float(torch.abs(y[2]).max()) == 0.0
+    for r in range(6):
+        y1, i1 = op.solve(b[r:r + 1].contiguous(), rtol=rtol, maxit=200, restart=12)
+        assert info[r]["converged"] and i1[0]["converged"], r
+        assert abs(info[r]["iters"] - i1[0]["iters"]) <= 1, (r, info[r]["iters"], i1[0]["iters"])
+        if r != 2:
+            assert info[r]["iters"] > 12   # several restart cycles
+            bar = 1e-9 if prec == "fp64" else 1e-3
+            assert _rel(y[r], y1[0]) < bar, r
+    op.close()
