@@ -13,6 +13,10 @@
 // iterations) is abandoned at its last good column and the solve goes on
 // from that iterate with the network switched off, M = D^-1 (a
 // "fallback").
+//
+// Each right-hand side is a resumable solve that stops at every operator
+// product it needs; several right-hand sides advance in lock-step and the
+// products of one step are performed as batched applies.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -160,22 +164,6 @@ struct Solver {
       return set_hip_error(e, "gmres norm copy");
     *out = std::sqrt(std::max(0.0, v.x));
     return 0;
-  }
-  // tmp = b - A x with the FP64 form of the operator (a plan running its
-  // FP32 form is switched for this one product and switched back), or with
-  // the working form when fp64 is false
-  int residual(const double2* b, const double2* x, bool fp64) {
-    ifgf_plan_t ip = nmuller_ifgf(nm);
-    int prev = IFGF_FP64;
-    int rc = fp64 ? ifgf_set_precision(ip, IFGF_FP64, &prev) : 0;
-    if (rc) return rc;
-    rc = nmuller_apply(nm, x, 1, tmp, st);
-    int rc2 = fp64 ? ifgf_set_precision(ip, prev, nullptr) : 0;
-    if (rc) return rc;
-    if (rc2) return rc2;
-    hipLaunchKernelGGL(k_axpy, dim3(nblk(m)), dim3(kBS), 0, st, make_double2(-1.0, 0.0), tmp, b, tmp, m);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? 0 : set_hip_error(e, "gmres residual");
   }
   // out (+)= sum_j B_j c_j for host coefficients c (out zeroed first if init0)
   int combine(const double2* Bb, const std::vector<cd>& c, int nj, double2* out, bool init0) {
