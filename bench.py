@@ -171,6 +171,54 @@ def batching(log, reps=5):
     return res
 
 
+def bodies32(log, reps=5):
+    """32 uneven ellipsoids (a, b, c ~ U[0.5, 3], eps_r ~ U[1.5, 4], seeds
+    1000 + i; patches per face ceil(sqrt(A / 1.5)) for surface area A, so a
+    patch is about (0.5 wavelengths)^2; 10 x 10 nodes), mixed form: 32 looped
+    applies vs one graph launch of all 32.  The host plans take minutes."""
+    import torch
+    import synth
+    from paper_2408_02274_amd import NMullerGraph, NMullerOperator
+    from paper_2408_02274_amd import binding as B
+
+    def area(a, b, c, p=1.6075):   # Knud Thomsen's approximation
+        return 4 * math.pi * (((a * b) ** p + (a * c) ** p + (b * c) ** p) / 3) ** (1 / p)
+
+    ops, ys, outs, npts = [], [], [], []
+    t0 = time.perf_counter()
+    for i, (a, b, c, eps) in enumerate(synth.ellipsoid_batch(32, 1000)):
+        npf = max(1, math.ceil(math.sqrt(area(a, b, c) / 1.5)))
+        s = synth.ellipsoid(a, b, c, npf, 10)
+        ops.append(NMullerOperator(s, 1.0, eps, tol=1e-4, precision=B.IFGF_FP32))
+        ys.append(torch.from_numpy(synth.complex_normal((1, 4, s.n), 100 + i)).to("cuda"))
+        outs.append(torch.empty_like(ys[-1]))
+        npts.append(s.n)
+        log(f"body {i}: n = {s.n}, plans {time.perf_counter() - t0:.0f} s")
+    plan_s = time.perf_counter() - t0
+
+    def clock(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    t_loop = clock(lambda: [op.apply(y, o) for op, y, o in zip(ops, ys, outs)])
+    g = NMullerGraph(ops, ys, outs)
+    t_graph = clock(g.launch)
+    res = {"workload": "32 ellipsoids, seeds 1000..1031, mixed form", "points_total": int(sum(npts)),
+           "points_min": int(min(npts)), "points_max": int(max(npts)), "plan_seconds": plan_s,
+           "ms_looped": t_loop * 1e3, "ms_graph": t_graph * 1e3, "batch_matvecs_per_s_graph": 1 / t_graph,
+           "body_matvecs_per_s_graph": 32 / t_graph, "graph_nodes": g.nodes}
+    g.close()
+    for op in ops:
+        op.close()
+    log(f"bodies32: {res}")
+    return res
+
+
 def learned_preconditioner(log, seed=5003):
     """The learned FGMRES preconditioner on a held-out body of the family it
     was trained on (ellipsoid semi-axes U[0.5, 2], eps_r U[2, 12], 6 x 6 x 6
@@ -231,12 +279,14 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solves")
     ap.add_argument("--ifgf-only", action="store_true",
                     help="time the raw IFGF sums only (no N-Mueller plan: seconds to set up)")
+    ap.add_argument("--bodies32", action="store_true",
+                    help="also time the 32-ellipsoid batch (host plans take ~5 minutes)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding across GPUs "
-              "is described in DESIGN.md and not built", file=sys.stderr)
+              "is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -403,6 +453,8 @@ def main():
     }
     if not args.no_batch and not args.ifgf_only:
         res["batching"] = batching(log)
+    if args.bodies32:
+        res["bodies32"] = bodies32(log)
     if not args.no_cpu:
         ks = (2 * math.pi * math.sqrt(eps_i), 2 * math.pi * math.sqrt(eps_e))
         w = np.full(surf.n, 4.0 * math.pi * args.radius ** 2 / surf.n) if args.ifgf_only else op.geometry(1)

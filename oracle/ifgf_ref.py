@@ -21,7 +21,7 @@ Follows Sec. III-E..III-I of the paper in its order and notation:
   * IFGF_Vec (Sec. III-I): one traversal for 8 densities x 2 kernels,
     normal derivative of the single-layer sums for densities 0..5.
 
-Readings where the text is silent or garbled (each also in the design doc):
+Readings where the text is silent or garbled:
   A1  leaf size uses the shorter wavelength 2 pi / max(k0, k1);
   A2  a_d uses max(k0, k1); A3 the cone rule counts from level D+1 down;
   A4  only the angular cone count doubles (refine_radial=True doubles n_s too);

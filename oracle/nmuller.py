@@ -141,7 +141,8 @@ def interior_field(nm: NMuller, y, X):
     """Total interior field (E, H) at points X [M, 3] strictly inside Gamma.
 
     From the representation that reproduces eq. n_muller through the jump
-    relations (reading A15, derived in the design doc):
+    relations (the interior Stratton-Chu representation with the surface
+    densities m and j):
       E_i = -omega mu_i curl S_i[m] - i (k_i^2 S_i[j] + grad S_i[div j])
       H_i = -omega eps_i curl S_i[j] + i (k_i^2 S_i[m] + grad S_i[div m])
     with S_i evaluated by the regular (Fejer) quadrature, valid away from Gamma.

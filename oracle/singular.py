@@ -19,7 +19,7 @@ Sec. III-B..III-D of the paper:
 Kernels K: G_k (single layer, S) and n_l . grad_x G_k (normal derivative, D,
 principal value on the smooth surface), for both wavenumbers.
 
-Readings (also in DESIGN.md):
+Readings:
   A10 delta_p = 1.0 x the diagonal of patch p's node bounding box;
   A11 N_beta = 6 Nc (even, so no Fejer node falls at tau = 0) and d = 4.  The
       paper chooses N_beta to match the IFGF accuracy; this product-map
