@@ -1,0 +1,47 @@
+"""bench.py's contract on the CPU: one-GPU refusal, the per-unit work figures
+the roofline uses, and the committed HBM-traffic summary it reads."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_per_unit_flops_at_orders_5_5():
+    npts = 5 * 5 * 5
+    # (parent point, child box) pair: 16 complex columns x npts real weights, centring, geometry
+    assert bench.flops_per_unit("propagate", npts) == 8400.0
+    # (target, cousin box) pair: value and normal-derivative rows, weights, epilogue
+    assert bench.flops_per_unit("targets", npts) == 15550.0
+    assert bench.flops_per_unit("unknown", npts) == 0.0
+    assert bench.bytes_per_unit("nm_correct") == 68.0
+
+
+def test_traffic_summary_is_read_only_for_its_workload_and_kernel(monkeypatch):
+    vals = {}
+    for line in open(bench.TRAFFIC):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != bench.kernel_sha():
+        pytest.skip("propagation source changed since the counters were taken")
+    t = bench.traffic_per_launch("propagate", "fp32", 153600, 5, 5)
+    assert t == float(vals["hbm_bytes_per_launch"]) and t > 0
+    assert bench.traffic_per_launch("propagate", "fp64", 153600, 5, 5) is None
+    assert bench.traffic_per_launch("propagate", "fp32", 6144, 5, 5) is None
+    assert bench.traffic_per_launch("propagate", "fp32", 153600, 3, 5) is None
+    assert bench.traffic_per_launch("targets", "fp32", 153600, 5, 5) is None
+    monkeypatch.setattr(bench, "kernel_sha", lambda *a: "0" * 64)
+    assert bench.traffic_per_launch("propagate", "fp32", 153600, 5, 5) is None
