@@ -36,6 +36,7 @@ extern "C" {
 #define IFGF_ENOMEM (-2)       /* host or device allocation failed             */
 #define IFGF_EHIP (-3)         /* HIP runtime error (message holds its string) */
 #define IFGF_ENOTPLANNED (-4)  /* operation needs a plan that was not built    */
+#define IFGF_EDEVICE (-5)      /* a kernel reported a failure (ifgf_check)     */
 #define IFGF_WNOCONV 1         /* GMRES stopped at maxit before the tolerance  */
 
 #define IFGF_FP64 0            /* cone grids, interpolation, sums in FP64      */
@@ -83,7 +84,11 @@ void ifgf_default_options(ifgf_options* opt);
  *  weights  host [n] FP64 quadrature weights (> 0), e.g. Fejer w_i w_j J_p
  *  k_int, k_ext  wavenumbers (> 0)
  *  tol      target relative accuracy in [1e-10, 1e-1]; selects Ps, Pa when
- *           the options leave them 0
+ *           the options leave them 0: tol >= 1e-3 -> (4, 5), >= 1e-4 ->
+ *           (5, 6), >= 1e-5 -> (7, 8), else (8, 8), the smallest orders
+ *           whose relative L2 error stayed below tol in every output block
+ *           (S and the normal-derivative sums separately) on the test
+ *           surfaces; below 1e-6 the largest orders do not reach tol
  *  opt      NULL = defaults
  * Errors: IFGF_EINVAL (bad sizes, NaN/Inf, non-unit normals, weights <= 0,
  * k <= 0, tol out of range, duplicate points), IFGF_ENOMEM, IFGF_EHIP.     */
@@ -133,9 +138,24 @@ int ifgf_autotune(ifgf_plan_t plan, void* stream, int* chosen);
 /* Switch the working precision of a built plan (IFGF_FP64 or IFGF_FP32)
  * for the following apply calls; `previous` (may be NULL) receives the one
  * in force before.  The FP64 and FP32 forms share the plan tables; FP32 is
- * available when Pa = 5 and 3 <= Ps <= 6 (else IFGF_EINVAL).  Used by the
+ * available when Pa = 5 or 6 and 3 <= Ps <= 6 (else IFGF_EINVAL).  Used by the
  * mixed-precision solve: Arnoldi on the FP32 form, residuals on the FP64.   */
 int ifgf_set_precision(ifgf_plan_t plan, int precision, int* previous);
+
+/* Device-side failures.  The FP32 propagation adds its tiles into a shared
+ * accumulator under a lock whose wait is bounded; a wavefront that gives up
+ * skips its tile and sets bit 0 of the plan's device error word, so that the
+ * sums are never silently wrong.  ifgf_check synchronises `stream`, copies
+ * the word to *flags (may be NULL), clears it, and returns IFGF_EDEVICE if it
+ * was set (the applies since the previous check are then incomplete).
+ * nmuller_solve checks after every solve; ifgf_stats reports the word.     */
+int ifgf_check(ifgf_plan_t plan, void* stream, unsigned* flags);
+
+/* Attempts of the bounded lock wait above (default 2^22, i.e. seconds of
+ * spinning, which a correct run never approaches).  For tests of the error
+ * path: 0 makes every locked add give up, and ifgf_check must then report
+ * IFGF_EDEVICE while every kernel still runs to its end.                   */
+int ifgf_set_lock_spin_limit(ifgf_plan_t plan, int limit);
 
 /* Switch per-kernel timing on (1) or off (0); either resets the totals.    */
 int ifgf_set_timing(ifgf_plan_t plan, int on);

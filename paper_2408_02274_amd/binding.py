@@ -18,10 +18,13 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libifgf.so")
 IFGF_FP64 = 0
 IFGF_FP32 = 1
 IFGF_WNOCONV = 1
+IFGF_EDEVICE = -5
 
 
 class IFGFError(RuntimeError):
-    pass
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 class Options(C.Structure):
@@ -69,6 +72,8 @@ def lib():
         L.ifgf_set_timing.restype = ci
         L.ifgf_set_precision.argtypes = [vp, ci, C.POINTER(ci)]
         L.ifgf_autotune.argtypes = [vp, vp, C.POINTER(ci)]
+        L.ifgf_check.argtypes = [vp, vp, C.POINTER(C.c_uint)]
+        L.ifgf_set_lock_spin_limit.argtypes = [vp, ci]
         L.ifgf_autotune.restype = ci
         L.ifgf_set_precision.restype = ci
         L.ifgf_destroy.argtypes = [vp]
@@ -117,7 +122,7 @@ def lib():
                      "nmuller_precond_pairs", "nmuller_patch_features", "mlp_create", "mlp_num_params",
                      "mlp_set_params", "mlp_get_params", "mlp_get_grad", "mlp_forward", "mlp_backward",
                      "mlp_adam_step", "mlp_train_step", "nmuller_graph_capture", "ifgf_graph_launch",
-                     "ifgf_graph_nodes"):
+                     "ifgf_graph_nodes", "ifgf_check", "ifgf_set_lock_spin_limit"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -137,7 +142,7 @@ def exported_symbols():
 
 def _check(rc, what):
     if rc < 0:
-        raise IFGFError(f"{what} failed ({rc}): {lib().ifgf_last_error().decode()}")
+        raise IFGFError(f"{what} failed ({rc}): {lib().ifgf_last_error().decode()}", rc)
     return rc
 
 
@@ -221,6 +226,18 @@ def ifgf_set_precision(plan, precision):
     prev = C.c_int(0)
     _check(lib().ifgf_set_precision(plan, int(precision), C.byref(prev)), "ifgf_set_precision")
     return prev.value
+
+
+def ifgf_check(plan, stream=None):
+    """Synchronise and read the plan's device error word; raises IFGFError
+    (code IFGF_EDEVICE) if a kernel reported a failure since the last check."""
+    flags = C.c_uint(0)
+    _check(lib().ifgf_check(plan, _stream_ptr(stream), C.byref(flags)), "ifgf_check")
+    return flags.value
+
+
+def ifgf_set_lock_spin_limit(plan, limit):
+    _check(lib().ifgf_set_lock_spin_limit(plan, int(limit)), "ifgf_set_lock_spin_limit")
 
 
 def ifgf_destroy(plan):

@@ -16,7 +16,7 @@ ARCH = os.environ.get("IFGF_OFFLOAD_ARCH", "gfx950")
 
 CXXFLAGS = ["-O2", "-fPIC", "-std=c++17", "-fopenmp", "-ffp-contract=off",
             f"-I{ROCM}/include", "-D__HIP_PLATFORM_AMD__", "-Wall", "-Wno-unused-function"]
-HIPFLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
+HIPFLAGS = ["-O3", "-fPIC", "-std=c++20", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-result", "-munsafe-fp-atomics"]
 

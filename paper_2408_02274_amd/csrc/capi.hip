@@ -88,7 +88,7 @@ struct ifgf_plan_s {
   double2* d_vals[2] = {nullptr, nullptr};
   int64_t max_slots = 0;
   PhaseTimer timer;
-  // matrix-core path (Pa = 5): K-slot cone layout, FP32 or FP64 cone data
+  // matrix-core path (Pa = 5 or 6): K-slot cone layout, FP32 or FP64 cone data
   bool mfma = false;
   bool fp32 = false;
   void* d_af = nullptr;                 // weighted densities of a batch [n][R][16]
@@ -97,6 +97,8 @@ struct ifgf_plan_s {
   std::vector<PropGroups> groups;       // groups[d]: propagation into level d
   std::vector<TargetTiles> ttiles;      // ttiles[d]: target pairs by cone (matrix-core interpolation)
   void* d_res = nullptr;                // per-pair target contributions [pairs][28] complex
+  unsigned* d_err = nullptr;            // device error word (bit 0: a propagation lock wait gave up)
+  int spin_limit = 1 << 22;             // attempts of the bounded lock wait
 };
 
 namespace ifgf {
@@ -109,13 +111,26 @@ bool timing_on(ifgf_plan_s* p) { return p && p->timer.on; }
 
 namespace {
 
+// Which kernel interpolates onto the cousin targets of level d: the
+// matrix-core tiles (one right-hand side per pass; levels whose pair count
+// fits the tile tables) or one thread per target otherwise.
+const char* target_path(const ifgf_plan_s* p, int d) {
+  if (!p->mfma) return "generic";
+  if (p->d_res && d < (int)p->ttiles.size() && p->ttiles[d].ntiles > 0) return "mfma_tiles";
+  return "per_target";
+}
+
 int tol_to_orders(double tol, int* Ps, int* Pa) {
-  // Paper setting (Remark 2): Ps = 3, Pa = 5.  Tighter tolerances raise the
-  // radial order first, which dominates the interpolation error.
-  if (tol >= 1e-3) { *Ps = 3; *Pa = 5; }
-  else if (tol >= 1e-4) { *Ps = 5; *Pa = 5; }
-  else if (tol >= 1e-5) { *Ps = 5; *Pa = 7; }
-  else { *Ps = 7; *Pa = 8; }
+  // The smallest orders whose interpolation error stays below tol in every
+  // output block (the single-layer sums and, larger, their normal
+  // derivatives, whose angular part needs Pa > 5 below 2.5e-4), measured
+  // against direct sums on spheres and an ellipsoid at 4-6 points per
+  // interior wavelength.  The paper's (3, 5) (Remark 2) is reachable by
+  // setting the orders explicitly.
+  if (tol >= 1e-3) { *Ps = 4; *Pa = 5; }
+  else if (tol >= 1e-4) { *Ps = 5; *Pa = 6; }
+  else if (tol >= 1e-5) { *Ps = 7; *Pa = 8; }
+  else { *Ps = 8; *Pa = 8; }
   return 0;
 }
 
@@ -273,7 +288,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   p->fp32 = opt.precision == IFGF_FP32;
   if (p->fp32 && !p->mfma) {
     delete p;
-    return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 and 3 <= Ps <= 6");
+    return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 or 6 and 3 <= Ps <= 6");
   }
   if (p->mfma)
     for (int d = 1; d <= H.D; ++d) std::vector<int32_t>().swap(H.lev[d].pp_slot);
@@ -356,14 +371,20 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     std::vector<int32_t>().swap(L.pp_slot);
   }
   // right-hand sides stacked into the cone-data columns (matrix-core path)
-  p->rcap = p->mfma ? std::min(std::min(opt.max_nrhs, opt.batch_columns), p->fp32 ? 4 : 2) : 1;
+  p->rcap = p->mfma ? std::min(std::min(opt.max_nrhs, opt.batch_columns), max_batch_columns(p->fp32, opt.Ps, opt.Pa))
+                    : 1;
   if (p->rcap == 3) p->rcap = 2;
   p->rsel = p->rcap;
   p->d_a = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kNS));
   p->d_out_s = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kOut * p->rcap));
-  if (!p->d_a || !p->d_out_s) {
+  p->d_err = static_cast<unsigned*>(ar.alloc(sizeof(unsigned)));
+  if (!p->d_a || !p->d_out_s || !p->d_err) {
     delete p;
     return set_error(IFGF_ENOMEM, "device workspace allocation failed");
+  }
+  if (hipError_t e = hipMemset(p->d_err, 0, sizeof(unsigned)); e != hipSuccess) {
+    delete p;
+    return set_hip_error(e, "hipMemset");
   }
   // A matrix-core plan can run in either precision (ifgf_set_precision), so
   // its FP32 density copy and FP64-sized cone buffers always exist.
@@ -382,7 +403,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     }
   }
   if (p->max_slots > 0) {
-    size_t vb = p->mfma ? sizeof(double) * (size_t)p->max_slots * kslot_rows(opt.Ps) * 32 * p->rcap
+    size_t vb = p->mfma ? sizeof(double) * (size_t)p->max_slots * kslot_rows(opt.Ps, opt.Pa) * 32 * p->rcap
                         : sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
     p->d_vals[0] = static_cast<double2*>(ar.alloc(vb));
     p->d_vals[1] = static_cast<double2*>(ar.alloc(vb));
@@ -409,7 +430,7 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
   PhaseTimer& T = p->timer;
   if (p->mfma && H.D >= 3) {
     // matrix-core path: R right-hand sides per pass share the geometry
-    const int rmax = std::min(p->rsel, max_batch_columns(p->fp32));
+    const int rmax = std::min(p->rsel, max_batch_columns(p->fp32, H.Ps, H.Pa));
     for (int r0 = 0; r0 < nrhs;) {
       const int rem = nrhs - r0;
       const int R = (rem >= 4 && rmax >= 4) ? 4 : ((rem >= 2 && rmax >= 2) ? 2 : 1);
@@ -431,7 +452,7 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
         return set_hip_error(e, "gather batch");
       int cur = 0;
       hipEvent_t ev = T.begin(st);
-      if ((e = mf_leaf(p->fp32, H.Ps, R, p->lev[H.D], p->ic, p->d_xs, p->d_af, k0, k1, p->d_vals[cur], st)) !=
+      if ((e = mf_leaf(p->fp32, H.Ps, H.Pa, R, p->lev[H.D], p->ic, p->d_xs, p->d_af, k0, k1, p->d_vals[cur], st)) !=
           hipSuccess)
         return set_hip_error(e, "leaf");
       T.end("leaf", ev, st, (double)H.leaf_pairs * R);
@@ -439,19 +460,20 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
         ev = T.begin(st);
         if (R == 1 && p->d_res && p->ttiles[d].ntiles > 0) {
           // cone-major tiles on the matrix cores, then the per-target sums
-          if ((e = mf_targets_tiles(p->fp32, H.Ps, p->lev[d], p->ic, p->ttiles[d], p->d_xs, p->d_nrm, k0, k1,
+          if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, p->lev[d], p->ic, p->ttiles[d], p->d_xs, p->d_nrm, k0, k1,
                                     p->d_vals[cur], p->d_res, st)) != hipSuccess ||
               (e = mf_targets_reduce(p->fp32, p->lev[d], n, p->d_res, p->d_out_s, st)) != hipSuccess)
             return set_hip_error(e, "targets");
-        } else if ((e = mf_targets(p->fp32, H.Ps, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1,
+        } else if ((e = mf_targets(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1,
                                    p->d_vals[cur], p->d_out_s, st)) != hipSuccess) {
           return set_hip_error(e, "targets");
         }
         T.end("targets", ev, st, (double)H.lev[d].tp_off.back() * R);
         if (d > 3) {
           ev = T.begin(st);
-          if ((e = mf_propagate(p->fp32, H.Ps, R, p->lev[d], p->lev[d - 1], p->ic, p->groups[d - 1], k0, k1,
-                                p->d_vals[cur], p->d_vals[cur ^ 1], st)) != hipSuccess)
+          if ((e = mf_propagate(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->lev[d - 1], p->ic, p->groups[d - 1], k0,
+                                k1, p->d_vals[cur], p->d_vals[cur ^ 1], p->spin_limit, p->d_err, st)) !=
+              hipSuccess)
             return set_hip_error(e, "propagate");
           T.end("propagate", ev, st, (double)H.lev[d - 1].pp_off.back() * R);
           cur ^= 1;
@@ -578,9 +600,13 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
          std::to_string(L.nb) + ",\"ns\":" + std::to_string(L.ns) + ",\"na\":" +
          std::to_string(L.na) + ",\"slots\":" + std::to_string(L.nslots) +
          ",\"prop_groups\":" + std::to_string(L.pg_off.empty() ? 0 : L.pg_off.back()) +
-         ",\"prop_tiles\":" + std::to_string(L.pt_off.empty() ? 0 : L.pt_off.back()) + "}";
+         ",\"prop_tiles\":" + std::to_string(L.pt_off.empty() ? 0 : L.pt_off.back()) +
+         ",\"target_path\":\"" + target_path(p, d) + "\"}";
   }
-  s += "],\"timing\":{";
+  unsigned derr = 0;
+  if (p->d_err && hipMemcpy(&derr, p->d_err, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
+    return set_error(IFGF_EHIP, "reading the device error word");
+  s += "],\"device_error\":" + std::to_string(derr) + ",\"timing\":{";
   p->timer.collect();
   bool first = true;
   for (auto& kv : p->timer.acc) {
@@ -604,7 +630,7 @@ int ifgf_autotune(ifgf_plan_t p, void* stream, int* chosen) {
   if (p->timer.on) return set_error(IFGF_EINVAL, "switch per-kernel timing off before tuning");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t n = p->host.n;
-  const int top = std::min(p->rcap, max_batch_columns(p->fp32));
+  const int top = std::min(p->rcap, max_batch_columns(p->fp32, p->host.Ps, p->host.Pa));
   int best = 1;
   if (p->mfma && top > 1) {
     DeviceArena tmp;
@@ -654,10 +680,35 @@ int ifgf_set_precision(ifgf_plan_t p, int precision, int* previous) {
     return set_error(IFGF_EINVAL, "precision must be IFGF_FP64 or IFGF_FP32");
   if (p->opt.host_only) return set_error(IFGF_ENOTPLANNED, "plan was built with host_only");
   if (precision == IFGF_FP32 && !p->mfma)
-    return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 and 3 <= Ps <= 6");
+    return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 or 6 and 3 <= Ps <= 6");
   if (previous) *previous = p->fp32 ? IFGF_FP32 : IFGF_FP64;
   p->fp32 = precision == IFGF_FP32;
   p->opt.precision = precision;
+  return IFGF_OK;
+}
+
+int ifgf_check(ifgf_plan_t p, void* stream, unsigned* flags) {
+  clear_error();
+  if (!p) return set_error(IFGF_EINVAL, "plan is NULL");
+  if (flags) *flags = 0;
+  if (p->opt.host_only || !p->d_err) return IFGF_OK;
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return set_hip_error(e, "hipStreamSynchronize");
+  unsigned w = 0;
+  if ((e = hipMemcpy(&w, p->d_err, sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess)
+    return set_hip_error(e, "hipMemcpy");
+  if (flags) *flags = w;
+  if (w == 0) return IFGF_OK;
+  if ((e = hipMemset(p->d_err, 0, sizeof(unsigned))) != hipSuccess) return set_hip_error(e, "hipMemset");
+  return set_error(IFGF_EDEVICE, "a propagation wavefront gave up waiting for its accumulator lock; "
+                                 "the sums of the applies since the last check are incomplete");
+}
+
+int ifgf_set_lock_spin_limit(ifgf_plan_t p, int limit) {
+  clear_error();
+  if (!p) return set_error(IFGF_EINVAL, "plan is NULL");
+  if (limit < 0) return set_error(IFGF_EINVAL, "limit must be >= 0");
+  p->spin_limit = limit;
   return IFGF_OK;
 }
 

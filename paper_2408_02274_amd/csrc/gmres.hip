@@ -556,6 +556,8 @@ extern "C" int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, i
       if (!Gs[i]->info().converged) status = IFGF_WNOCONV;
     }
   }
+  // a device-side failure of any apply makes the whole solve suspect
+  if ((rc = ifgf_check(nmuller_ifgf(nm), stream, nullptr))) return rc;
   return status;
 }
 
@@ -585,5 +587,6 @@ extern "C" int nmuller_solve_trajectory(nmuller_t nm, const void* rhs, void* y, 
   if ((rc = run_one(G, nm, S.m, S.st))) return rc;
   *nrec = rec.count;
   if (info) *info = G.info();
+  if ((rc = ifgf_check(nmuller_ifgf(nm), stream, nullptr))) return rc;
   return G.info().converged ? IFGF_OK : IFGF_WNOCONV;
 }

@@ -5,16 +5,17 @@
 // and 3b (interpolation onto parent interpolation points times the
 // re-centring factor G(X, x_child) / G(X, x_parent), summed over children).
 //
-// Cone data layout ("K-slot" order, Pa = 5).  A cone with Ps x 5 x 5 nodes
-// (a, b, c) -> point p = 5 (5 a + b) + c is stored as K = 4 * KS rows with
-// KS = nab + ceil(nab / 4), nab = 5 Ps:
-//   c < 4 : row 4 * ab + c           (ab = 5 a + b)
-//   c = 4 : row 4 * nab + ab
+// Cone data layout ("K-slot" order, Pa = 5 or 6).  A cone with Ps x Pa x Pa
+// nodes (a, b, c) -> point p = Pa (Pa a + b) + c is stored as K = 4 * KS rows
+// with nab = Pa Ps, tc = Pa - 4 and KS = nab + ceil(tc nab / 4):
+//   c < 4  : row 4 * ab + c                      (ab = Pa a + b)
+//   c >= 4 : row 4 * nab + tc * ab + (c - 4)
 // remaining rows are zero padding.  A row holds R groups of 32 reals, one
 // group per right-hand side of the batch: the real parts of the 16 complex
-// columns (column = 8 * kernel + density) then their imaginary parts.  With this order the MFMA lane group g = lane / 16 always supplies
-// the phi-node c = g (first nab k-steps) so the interpolation weight of a
-// lane is one product of per-point Lagrange factors.
+// columns (column = 8 * kernel + density) then their imaginary parts.  With
+// this order the MFMA lane group g = lane / 16 supplies the phi-node c = g in
+// the first nab k-steps and c = 4 + g mod tc in the others, so the
+// interpolation weight of a lane is one product of per-point Lagrange factors.
 //
 // The interpolant is the tensor Chebyshev interpolant of Sec. III-F in
 // Lagrange form on the same nodes (identical polynomial).  Geometry is
@@ -114,13 +115,13 @@ __device__ __forceinline__ void lag_d(const X* x, const X* w, T u, T* dL) {
 }
 
 // node (s, theta, phi) of point p of cone `cone` and the unit direction
-template <int PS, class T>
+template <int PA, class T>
 __device__ __forceinline__ void cone_node(int ns, int na, int cone, int p, const InterpC& ic, T* s,
                                           T* ux, T* uy, T* uz) {
   const int ip = cone % (2 * na);
   const int it = (cone / (2 * na)) % na;
   const int is = cone / (2 * na * na);
-  const int c = p % 5, b = (p / 5) % 5, a = p / 25;
+  const int c = p % PA, b = (p / PA) % PA, a = p / (PA * PA);
   const double ds = kEtaD / ns, da = kPiD / na;
   *s = (T)((is + 0.5) * ds + 0.5 * ds * ic.xs[a]);
   T t = (T)((it + 0.5) * da + 0.5 * da * ic.xa[b]);
@@ -163,14 +164,35 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
-__device__ __forceinline__ int point_of_row(int row, int nab) {
-  if (row < 4 * nab) return 5 * (row >> 2) + (row & 3);
-  int m = row - 4 * nab;
-  return m < nab ? 5 * m + 4 : -1;
+// K-slot geometry of a Ps x PA x PA cone
+template <int PS, int PA> struct KSlot {
+  static constexpr int NAB = PS * PA;               // (radial, polar) node pairs
+  static constexpr int TC = PA - 4;                 // phi-nodes past the first four
+  static constexpr int KS = NAB + (TC * NAB + 3) / 4;
+  static constexpr int K = 4 * KS;
+  static constexpr int NPTS = NAB * PA;
+};
+
+// LDS of the propagation kernel: accumulator, per-wavefront geometry records
+// (4 x 64 lanes x (10 + 2 Pa) values), parent-point geometry, lock
+constexpr int64_t prop_lds_bytes(int Ps, int Pa, int R, int elem) {
+  return (int64_t)Ps * Pa * Pa * (32 * R + 1) * elem + 4 * 64 * (10 + 2 * Pa) * elem +
+         (int64_t)Ps * Pa * Pa * 4 * elem + 4;
 }
+constexpr int64_t kLdsLimit = 160 * 1024;
+
+template <int PA>
+__device__ __forceinline__ int point_of_row(int row, int nab) {
+  constexpr int TC = PA - 4;
+  if (row < 4 * nab) return PA * (row >> 2) + (row & 3);
+  const int m = row - 4 * nab;
+  return m < TC * nab ? PA * (m / TC) + 4 + m % TC : -1;
+}
+template <int PA>
 __device__ __forceinline__ int row_of_point(int p, int nab) {
-  int c = p % 5, ab = p / 5;
-  return c < 4 ? 4 * ab + c : 4 * nab + ab;
+  constexpr int TC = PA - 4;
+  const int c = p % PA, ab = p / PA;
+  return c < 4 ? 4 * ab + c : 4 * nab + TC * ab + (c - 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -190,18 +212,18 @@ __global__ void k_gather(const double2* __restrict__ dens, const int64_t* __rest
 }
 
 // leaf cone values: thread per (slot, row, right-hand side)
-template <int PS, class T, int R>
+template <int PS, int PA, class T, int R>
 __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const double* __restrict__ xs, const T* __restrict__ a,
                          double k0, double k1, T* __restrict__ V) {
-  constexpr int NAB = PS * 5;
-  constexpr int K = 4 * (NAB + (NAB + 3) / 4);
+  constexpr int NAB = KSlot<PS, PA>::NAB;
+  constexpr int K = KSlot<PS, PA>::K;
   int64_t t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= L.nslots * K * R) return;
   int64_t q = t / (K * R);
   int row = (int)((t / R) % K);
   const int r = (int)(t % R);
   T* o = V + t * 32;
-  int p = point_of_row(row, NAB);
+  int p = point_of_row<PA>(row, NAB);
   if (p < 0) {
 #pragma unroll
     for (int c = 0; c < 32; ++c) o[c] = (T)0;
@@ -210,7 +232,7 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
   int32_t b = L.slot_box[q];
   const double* c = L.centers + 3 * b;
   T s, ux, uy, uz;
-  cone_node<PS, T>(L.ns, L.na, L.slot_cone[q], p, ic, &s, &ux, &uy, &uz);
+  cone_node<PA, T>(L.ns, L.na, L.slot_cone[q], p, ic, &s, &ux, &uy, &uz);
   const T rxc = (T)L.h / s;
   const T Yx = rxc * ux, Yy = rxc * uy, Yz = rxc * uz;
   T acc[32];
@@ -247,15 +269,19 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
 // wavefronts.  A wavefront takes its tiles four at a time: one lane per point
 // evaluates the child-cone coordinates, Lagrange factors and re-centring
 // factor of its point into wave-private LDS, then the four MFMA tiles run.
-template <int PS, class T, int R>
+template <int PS, int PA, class T, int R>
 __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, InterpC ic, PropGroups G,
                                                    double k0, double k1, const T* __restrict__ Vc,
-                                                   T* __restrict__ Vp) {
-  constexpr int NAB = PS * 5;
-  constexpr int KS = NAB + (NAB + 3) / 4;
-  constexpr int K = 4 * KS;
-  constexpr int NPTS = NAB * 5;
-  constexpr int GW = 20;                // Ls [0, PS), Lt [6, 11), Lp [11, 16), factor [16, 20)
+                                                   T* __restrict__ Vp, int spin_limit,
+                                                   unsigned* __restrict__ err) {
+  constexpr int NAB = KSlot<PS, PA>::NAB;
+  constexpr int TC = KSlot<PS, PA>::TC;
+  constexpr int KS = KSlot<PS, PA>::KS;
+  constexpr int K = KSlot<PS, PA>::K;
+  constexpr int NPTS = KSlot<PS, PA>::NPTS;
+  // per-lane geometry record: Ls [0, PS), Lt [OT, OT + PA), Lp [OP, OP + PA),
+  // re-centring factors [OF, OF + 4)
+  constexpr int OT = 6, OP = OT + PA, OF = OP + PA, GW = OF + 4;
   constexpr int W = 32 * R;             // reals per cone row
   __shared__ T acc[NPTS][W + 1];
   __shared__ T gbuf[4][64][GW];         // per wavefront: 4 tiles x 16 rows
@@ -272,7 +298,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   const double* cp = P.centers + 3 * pb;
   if (tid < NPTS) {
     T s, ux, uy, uz;
-    cone_node<PS, T>(P.ns, P.na, pcone, tid, ic, &s, &ux, &uy, &uz);
+    cone_node<PA, T>(P.ns, P.na, pcone, tid, ic, &s, &ux, &uy, &uz);
     const T rp = (T)P.h / s;
     geo[tid][0] = rp * ux;
     geo[tid][1] = rp * uy;
@@ -341,17 +367,17 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         const T us = (T)C.h * rci * two_ds - (T)(2 * is + 1);
         const T ut = th * two_da - (T)(2 * it + 1);
         const T up = ph * two_da - (T)(2 * ip + 1);
-        T L[PS], Lt[5], Lp[5];
+        T L[PS], Lt[PA], Lp[PA];
         lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, L);
-        lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
-        lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
+        lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
+        lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
         const T vm = valid ? (T)1 : (T)0;
 #pragma unroll
         for (int z = 0; z < PS; ++z) gb[lane][z] = L[z] * vm;
 #pragma unroll
-        for (int z = 0; z < 5; ++z) {
-          gb[lane][6 + z] = Lt[z];
-          gb[lane][11 + z] = Lp[z];
+        for (int z = 0; z < PA; ++z) {
+          gb[lane][OT + z] = Lt[z];
+          gb[lane][OP + z] = Lp[z];
         }
         // re-centring factor G(X, x_child) / G(X, x_parent) = (rp / rc) exp(i k (rc - rp))
         const T diff = (dx * dx + dy * dy + dz * dz - (T)2 * (Yx * dx + Yy * dy + Yz * dz)) / (rc + rp);
@@ -360,8 +386,8 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         for (int qq = 0; qq < 2; ++qq) {
           T sn, cs;
           tsincos<T>(kk[qq] * diff, &sn, &cs);
-          gb[lane][16 + 2 * qq] = ratio * cs;
-          gb[lane][17 + 2 * qq] = ratio * sn;
+          gb[lane][OF + 2 * qq] = ratio * cs;
+          gb[lane][OF + 1 + 2 * qq] = ratio * sn;
         }
       }
     }
@@ -374,16 +400,17 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       const int cnt = rb[b].w & 31;
       const T* Vs = Vc + (int64_t)rb[b].x * K * W + gl * W;
       const T* me = gb[16 * b + r16];
-      T Ls[PS], Lt[5];
+      T Ls[PS], Lt[PA];
 #pragma unroll
       for (int z = 0; z < PS; ++z) Ls[z] = me[z];
 #pragma unroll
-      for (int z = 0; z < 5; ++z) Lt[z] = me[6 + z];
-      const T lpg = me[11 + gl];
-      const T lp4 = me[15];
+      for (int z = 0; z < PA; ++z) Lt[z] = me[OT + z];
+      const T lpg = me[OP + gl];
+      // phi-node of this lane in the tail k-steps: 4 + gl mod tc
+      const T lp4 = me[OP + 4 + (TC == 1 ? 0 : (gl & 1))];
       T st[NAB];
 #pragma unroll
-      for (int ab = 0; ab < NAB; ++ab) st[ab] = Ls[ab / 5] * Lt[ab % 5];
+      for (int ab = 0; ab < NAB; ++ab) st[ab] = Ls[ab / PA] * Lt[ab % PA];
       typename MF<T>::acc c0[R], c1[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -395,13 +422,19 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         T av;
         if (j < NAB) {
           av = st[j] * lpg;
-        } else {
+        } else if constexpr (TC == 1) {
           // slot 4 j + gl holds phi-node 4 of (a, b) pair m = 4 (j - NAB) + gl
           const int m0 = 4 * (j - NAB);
           T sel = (m0 < NAB) ? st[m0 < NAB ? m0 : 0] : (T)0;
           sel = (gl == 1) ? ((m0 + 1 < NAB) ? st[m0 + 1 < NAB ? m0 + 1 : 0] : (T)0) : sel;
           sel = (gl == 2) ? ((m0 + 2 < NAB) ? st[m0 + 2 < NAB ? m0 + 2 : 0] : (T)0) : sel;
           sel = (gl == 3) ? ((m0 + 3 < NAB) ? st[m0 + 3 < NAB ? m0 + 3 : 0] : (T)0) : sel;
+          av = sel * lp4;
+        } else {
+          // slot 4 j + gl holds phi-node 4 + (gl & 1) of pair m = 2 (j - NAB) + gl / 2
+          const int m0 = 2 * (j - NAB);
+          T sel = (m0 < NAB) ? st[m0 < NAB ? m0 : 0] : (T)0;
+          sel = (gl >= 2) ? ((m0 + 1 < NAB) ? st[m0 + 1 < NAB ? m0 + 1 : 0] : (T)0) : sel;
           av = sel * lp4;
         }
         const T* vrow = Vs + (int64_t)(4 * j) * W;
@@ -421,7 +454,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
           const int orow = MF<T>::row(lane, e);
           po[e] = __builtin_amdgcn_ds_bpermute((16 * b + orow) << 2, pme);
           const int ro = orow < cnt ? orow : 0;
-          const T fr = gb[16 * b + ro][16 + 2 * qq], fi = gb[16 * b + ro][17 + 2 * qq];
+          const T fr = gb[16 * b + ro][OF + 2 * qq], fi = gb[16 * b + ro][OF + 1 + 2 * qq];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const T vr = c0[r][e], vi = c1[r][e];
@@ -433,43 +466,53 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         // with plain loads and stores; other wavefronts of the block add tiles
         // of other child boxes into the same points, hence the block lock
         // around the read-add-write (cheaper than per-element LDS atomics).
+        // The wait is bounded (spin_limit attempts).  A wavefront that gives up
+        // neither adds its tile nor releases the lock; it records the failure
+        // in the device error word, which the host turns into IFGF_EDEVICE.
+        int got = 0;
         if (lane == 0) {
           int expected = 0;
 #pragma unroll 1
-          for (int spin = 0; spin < (1 << 22); ++spin) {   // bounded: the wait always ends
+          for (int spin = 0; spin < spin_limit; ++spin) {
             if (__hip_atomic_compare_exchange_strong(&acc_lock, &expected, 1, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP)) {
+              got = 1;
               break;
+            }
             expected = 0;
             __builtin_amdgcn_s_sleep(1);
           }
+          if (!got) atomicOr(err, 1u);
         }
+        got = __builtin_amdgcn_readfirstlane(got);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        T oldr[4][R], oldi[4][R];
+        if (got) {
+          T oldr[4][R], oldi[4][R];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (MF<T>::row(lane, e) < cnt) {
+          for (int e = 0; e < 4; ++e) {
+            if (MF<T>::row(lane, e) < cnt) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              oldr[e][r] = acc[po[e]][32 * r + r16];
-              oldi[e][r] = acc[po[e]][32 * r + 16 + r16];
+              for (int r = 0; r < R; ++r) {
+                oldr[e][r] = acc[po[e]][32 * r + r16];
+                oldi[e][r] = acc[po[e]][32 * r + 16 + r16];
+              }
             }
           }
-        }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (MF<T>::row(lane, e) < cnt) {
+          for (int e = 0; e < 4; ++e) {
+            if (MF<T>::row(lane, e) < cnt) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              acc[po[e]][32 * r + r16] = oldr[e][r] + zr[e][r];
-              acc[po[e]][32 * r + 16 + r16] = oldi[e][r] + zi[e][r];
+              for (int r = 0; r < R; ++r) {
+                acc[po[e]][32 * r + r16] = oldr[e][r] + zr[e][r];
+                acc[po[e]][32 * r + 16 + r16] = oldi[e][r] + zi[e][r];
+              }
             }
           }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) __hip_atomic_store(&acc_lock, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) __hip_atomic_store(&acc_lock, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       } else {
         // FP64: native LDS add of doubles, no lock (the extra registers of
         // the locked form would halve the occupancy of this kernel)
@@ -478,7 +521,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
           const int orow = MF<T>::row(lane, e);
           const int pe = __builtin_amdgcn_ds_bpermute((16 * b + orow) << 2, pme);
           if (orow < cnt) {
-            const T fr = gb[16 * b + orow][16 + 2 * qq], fi = gb[16 * b + orow][17 + 2 * qq];
+            const T fr = gb[16 * b + orow][OF + 2 * qq], fi = gb[16 * b + orow][OF + 1 + 2 * qq];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
               const T vr = c0[r][e], vi = c1[r][e];
@@ -499,7 +542,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   T* out = Vp + q * (int64_t)K * W;
   for (int i = tid; i < K * W; i += 256) {
     const int row = i / W, col = i % W;
-    const int p = point_of_row(row, NAB);
+    const int p = point_of_row<PA>(row, NAB);
     out[i] = p >= 0 ? acc[p][col] : (T)0;
   }
 }
@@ -509,13 +552,13 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 // wavenumber q (the 16 columns of a cone row split 8 + 8 by kernel); each
 // loops over the target's cousin cones.  blockIdx.y selects the right-hand
 // side r of the batch of R.
-template <int PS, class T, int R>
+template <int PS, int PA, class T, int R>
 __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const double* __restrict__ xs,
                             const double* __restrict__ nrm, int64_t n, double k0, double k1,
                             const T* __restrict__ V, double2* __restrict__ out_s) {
-  constexpr int NAB = PS * 5;
-  constexpr int KS = NAB + (NAB + 3) / 4;
-  constexpr int K = 4 * KS;
+  constexpr int NAB = KSlot<PS, PA>::NAB;
+  constexpr int TC = KSlot<PS, PA>::TC;
+  constexpr int K = KSlot<PS, PA>::K;
   const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t i = g >> 1;
   const int q = (int)(g & 1);
@@ -539,13 +582,13 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
     const T zx = (T)(xs[3 * i] - c[0]), zy = (T)(xs[3 * i + 1] - c[1]), zz = (T)(xs[3 * i + 2] - c[2]);
     T r, us, ut, up, th, ph;
     local3<T>(zx, zy, zz, (T)L.h, L.ns, L.na, cone, &r, &us, &ut, &up, &th, &ph);
-    T Ls[PS], Lt[5], Lp[5], dLs[PS], dLt[5], dLp[5];
+    T Ls[PS], Lt[PA], Lp[PA], dLs[PS], dLt[PA], dLp[PA];
     lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, Ls);
-    lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
-    lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
+    lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
+    lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
     lag_d<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, dLs);
-    lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, dLt);
-    lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, dLp);
+    lag_d<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, dLt);
+    lag_d<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, dLp);
     const T rinv = (T)1 / r;
     const T n_r = (nx * zx + ny * zy + nz * zz) * rinv;
     T st, ct, sp, cp;
@@ -577,26 +620,26 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
         dLs[z] = dLs[z + 1];
       }
 #pragma unroll
-      for (int b = 0; b < 5; ++b) {
-        const int ab = 5 * a + b;
+      for (int b = 0; b < PA; ++b) {
+        const int ab = PA * a + b;
         const T lst = la * Lt[b];
         const T dst = c_s * dla * Lt[b] + c_t * la * dLt[b];
         const T phs = c_ph * la * Lt[b];
-        // phi index cc in a rolled loop; Lp/dLp rotate cyclically (restored after 5 steps)
+        // phi index cc in a rolled loop; Lp/dLp rotate cyclically (restored after PA steps)
 #pragma unroll 1
-        for (int cc = 0; cc < 5; ++cc) {
-          const int row = cc < 4 ? 4 * ab + cc : 4 * NAB + ab;
+        for (int cc = 0; cc < PA; ++cc) {
+          const int row = cc < 4 ? 4 * ab + cc : 4 * NAB + TC * ab + (cc - 4);
           const T w = lst * Lp[0];
           const T wd = dst * Lp[0] + phs * dLp[0];
           {
             const T l0 = Lp[0], d0 = dLp[0];
 #pragma unroll
-            for (int z = 0; z < 4; ++z) {
+            for (int z = 0; z + 1 < PA; ++z) {
               Lp[z] = Lp[z + 1];
               dLp[z] = dLp[z + 1];
             }
-            Lp[4] = l0;
-            dLp[4] = d0;
+            Lp[PA - 1] = l0;
+            dLp[PA - 1] = d0;
           }
           const T* vr = Vs + (int64_t)row * 32 * R;
 #pragma unroll
@@ -652,18 +695,19 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
 // applies the centred factor G(x, x_B) and its gradient and writes the 28
 // complex contributions of each (target, cousin) pair to res; a second
 // kernel sums them per target.
-template <int PS, class T>
+template <int PS, int PA, class T>
 __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, TargetTiles TT,
                                                       const double* __restrict__ xs,
                                                       const double* __restrict__ nrm, double k0, double k1,
                                                       const T* __restrict__ V, T* __restrict__ res) {
-  constexpr int NAB = PS * 5;
-  constexpr int KS = NAB + (NAB + 3) / 4;
-  constexpr int K = 4 * KS;
+  constexpr int NAB = KSlot<PS, PA>::NAB;
+  constexpr int TC = KSlot<PS, PA>::TC;
+  constexpr int KS = KSlot<PS, PA>::KS;
+  constexpr int K = KSlot<PS, PA>::K;
   // per-target record: Ls, c_s dLs, Lt, c_t dLt, Lp, c_ph dLp, then
   // Re G_q, Im G_q (q = 0, 1), -n.r-hat / r, n.r-hat
-  constexpr int OLS = 0, OSD = PS, OLT = 2 * PS, OTD = 2 * PS + 5, OLP = 2 * PS + 10, OPD = 2 * PS + 15,
-                OG = 2 * PS + 20, TW = 2 * PS + 26;
+  constexpr int OLS = 0, OSD = PS, OLT = 2 * PS, OTD = 2 * PS + PA, OLP = 2 * PS + 2 * PA,
+                OPD = 2 * PS + 3 * PA, OG = 2 * PS + 4 * PA, TW = OG + 6;
   __shared__ T rec[4][8][TW];
   __shared__ T outb[4][16][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -684,13 +728,13 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
       const T zx = (T)(xs[3 * i] - c[0]), zy = (T)(xs[3 * i + 1] - c[1]), zz = (T)(xs[3 * i + 2] - c[2]);
       T r, us, ut, up, th, ph;
       local3<T>(zx, zy, zz, (T)L.h, L.ns, L.na, cone, &r, &us, &ut, &up, &th, &ph);
-      T Ls[PS], Lt[5], Lp[5], dLs[PS], dLt[5], dLp[5];
+      T Ls[PS], Lt[PA], Lp[PA], dLs[PS], dLt[PA], dLp[PA];
       lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, Ls);
-      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
-      lag<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
+      lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, Lt);
+      lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, Lp);
       lag_d<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us, dLs);
-      lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, dLt);
-      lag_d<5, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, dLp);
+      lag_d<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut, dLt);
+      lag_d<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up, dLp);
       const T rinv = (T)1 / r;
       const T n_r = (nx * zx + ny * zy + nz * zz) * rinv;
       T sth, cth, sph, cph;
@@ -710,7 +754,7 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
         o[OSD + z] = c_s * dLs[z];
       }
 #pragma unroll
-      for (int z = 0; z < 5; ++z) {
+      for (int z = 0; z < PA; ++z) {
         o[OLT + z] = Lt[z];
         o[OTD + z] = c_t * dLt[z];
         o[OLP + z] = Lp[z];
@@ -739,7 +783,7 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   const int t = r16 >> 1;
   const T kv = (r16 & 1) ? (T)0 : (T)1, kd = (T)1 - kv;
   const T* me = rw[t];
-  T U[PS], W[PS], Ltv[5], Tdv[5];
+  T U[PS], W[PS], Ltv[PA], Tdv[PA];
   {
     const T f1 = kv * me[OLP + gl] + kd * me[OPD + gl], f2 = kd * me[OLP + gl];
 #pragma unroll
@@ -748,24 +792,26 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
       W[a] = me[OLS + a] * f2;
     }
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
+    for (int b = 0; b < PA; ++b) {
       Ltv[b] = me[OLT + b];
       Tdv[b] = me[OTD + b];
     }
   }
-  const T g1 = kv * me[OLP + 4] + kd * me[OPD + 4], g2 = kd * me[OLP + 4];
+  // phi-node of this lane in the tail k-steps: 4 + gl mod tc
+  const int ct4 = 4 + (TC == 1 ? 0 : (gl & 1));
+  const T g1 = kv * me[OLP + ct4] + kd * me[OPD + ct4], g2 = kd * me[OLP + ct4];
   typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
   const T* Vs = V + (int64_t)slot * K * 32 + gl * 32;
 #pragma unroll
   for (int j = 0; j < KS; ++j) {
     T av;
     if (j < NAB) {
-      av = Ltv[j % 5] * U[j / 5] + Tdv[j % 5] * W[j / 5];   // (a, b) = j, phi-node gl
+      av = Ltv[j % PA] * U[j / PA] + Tdv[j % PA] * W[j / PA];   // (a, b) = j, phi-node gl
     } else {
-      const int ab = 4 * (j - NAB) + gl;                   // phi-node 4 of pair ab
+      const int ab = (4 * (j - NAB) + gl) / TC;                // phi-node ct4 of pair ab
       if (ab < NAB) {
-        const T lsa = me[OLS + ab / 5], sda = me[OSD + ab / 5];
-        av = me[OLT + ab % 5] * (lsa * g1 + sda * g2) + me[OTD + ab % 5] * lsa * g2;
+        const T lsa = me[OLS + ab / PA], sda = me[OSD + ab / PA];
+        av = me[OLT + ab % PA] * (lsa * g1 + sda * g2) + me[OTD + ab % PA] * lsa * g2;
       } else {
         av = (T)0;
       }
@@ -827,141 +873,132 @@ __global__ void __launch_bounds__(256) k_targets_reduce(const int64_t* __restric
 
 inline unsigned nblk(int64_t w, int bs) { return (unsigned)((w + bs - 1) / bs); }
 
-template <int PS, class T, int R>
+template <int PS, int PA, class T, int R>
 hipError_t leaf_t(const DevLevel& L, const InterpC& ic, const double* xs, const void* a, double k0,
                   double k1, void* V, hipStream_t st) {
-  constexpr int NAB = PS * 5;
-  constexpr int K = 4 * (NAB + (NAB + 3) / 4);
+  constexpr int K = KSlot<PS, PA>::K;
   int64_t work = L.nslots * K * R;
   if (work <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_leaf_k<PS, T, R>), dim3(nblk(work, 256)), dim3(256), 0, st, L, ic, xs,
+  hipLaunchKernelGGL((k_leaf_k<PS, PA, T, R>), dim3(nblk(work, 256)), dim3(256), 0, st, L, ic, xs,
                      static_cast<const T*>(a), k0, k1, static_cast<T*>(V));
   return hipGetLastError();
 }
-template <int PS, class T, int R>
+template <int PS, int PA, class T, int R>
 hipError_t prop_t(const DevLevel& C, const DevLevel& P, const InterpC& ic, const PropGroups& G,
-                  double k0, double k1, const void* Vc, void* Vp, hipStream_t st) {
-  if (P.nslots <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_prop_mfma<PS, T, R>), dim3((unsigned)P.nslots), dim3(256), 0, st, C, P, ic, G, k0, k1,
-                     static_cast<const T*>(Vc), static_cast<T*>(Vp));
-  return hipGetLastError();
+                  double k0, double k1, const void* Vc, void* Vp, int spin_limit, unsigned* err,
+                  hipStream_t st) {
+  if constexpr (prop_lds_bytes(PS, PA, R, sizeof(T)) > kLdsLimit) {
+    return hipErrorInvalidValue;   // excluded by max_batch_columns
+  } else {
+    if (P.nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_prop_mfma<PS, PA, T, R>), dim3((unsigned)P.nslots), dim3(256), 0, st, C, P, ic, G, k0,
+                       k1, static_cast<const T*>(Vc), static_cast<T*>(Vp), spin_limit, err);
+    return hipGetLastError();
+  }
 }
-template <int PS, class T, int R>
+template <int PS, int PA, class T, int R>
 hipError_t targets_t(const DevLevel& L, const InterpC& ic, const double* xs, const double* nrm,
                      int64_t n, double k0, double k1, const void* V, double2* out_s, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_targets_k<PS, T, R>), dim3(nblk(2 * n, 64), R), dim3(64), 0, st, L, ic, xs, nrm, n, k0, k1,
-                     static_cast<const T*>(V), out_s);
+  hipLaunchKernelGGL((k_targets_k<PS, PA, T, R>), dim3(nblk(2 * n, 64), R), dim3(64), 0, st, L, ic, xs, nrm, n, k0,
+                     k1, static_cast<const T*>(V), out_s);
   return hipGetLastError();
+}
+template <int PS, int PA, class T>
+hipError_t targets_tiles_t(const DevLevel& L, const InterpC& ic, const TargetTiles& TT, const double* xs,
+                           const double* nrm, double k0, double k1, const void* V, void* res, hipStream_t st) {
+  if (TT.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_targets_mfma<PS, PA, T>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT, xs, nrm,
+                     k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+  return hipGetLastError();
+}
+
+// Calls f.template operator()<PS, PA>() for the supported orders (Pa = 5 or
+// 6, 3 <= Ps <= 6); hipErrorInvalidValue otherwise.
+template <class F>
+hipError_t with_orders(int Ps, int Pa, F&& f) {
+  if (Pa == 5) {
+    switch (Ps) {
+      case 3: return f.template operator()<3, 5>();
+      case 4: return f.template operator()<4, 5>();
+      case 5: return f.template operator()<5, 5>();
+      case 6: return f.template operator()<6, 5>();
+    }
+  } else if (Pa == 6) {
+    switch (Ps) {
+      case 3: return f.template operator()<3, 6>();
+      case 4: return f.template operator()<4, 6>();
+      case 5: return f.template operator()<5, 6>();
+      case 6: return f.template operator()<6, 6>();
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 // R = 1, 2 or 4 right-hand sides per pass; FP64 takes at most 2 (the LDS of
 // the propagation at R = 4 would exceed a workgroup's 160 KB)
-template <int PS, class T>
-hipError_t leaf_r(int R, const DevLevel& L, const InterpC& ic, const double* xs, const void* a, double k0,
-                  double k1, void* V, hipStream_t st) {
+template <class T, class F>
+hipError_t with_columns(int R, F&& f) {
   switch (R) {
-    case 1: return leaf_t<PS, T, 1>(L, ic, xs, a, k0, k1, V, st);
-    case 2: return leaf_t<PS, T, 2>(L, ic, xs, a, k0, k1, V, st);
+    case 1: return f.template operator()<1>();
+    case 2: return f.template operator()<2>();
     case 4:
-      if constexpr (std::is_same<T, float>::value) return leaf_t<PS, T, 4>(L, ic, xs, a, k0, k1, V, st);
-      break;
-  }
-  return hipErrorInvalidValue;
-}
-template <int PS, class T>
-hipError_t prop_r(int R, const DevLevel& C, const DevLevel& P, const InterpC& ic, const PropGroups& G,
-                  double k0, double k1, const void* Vc, void* Vp, hipStream_t st) {
-  switch (R) {
-    case 1: return prop_t<PS, T, 1>(C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 2: return prop_t<PS, T, 2>(C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 4:
-      if constexpr (std::is_same<T, float>::value) return prop_t<PS, T, 4>(C, P, ic, G, k0, k1, Vc, Vp, st);
-      break;
-  }
-  return hipErrorInvalidValue;
-}
-template <int PS, class T>
-hipError_t targets_r(int R, const DevLevel& L, const InterpC& ic, const double* xs, const double* nrm,
-                     int64_t n, double k0, double k1, const void* V, double2* out_s, hipStream_t st) {
-  switch (R) {
-    case 1: return targets_t<PS, T, 1>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 2: return targets_t<PS, T, 2>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 4:
-      if constexpr (std::is_same<T, float>::value)
-        return targets_t<PS, T, 4>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+      if constexpr (std::is_same<T, float>::value) return f.template operator()<4>();
       break;
   }
   return hipErrorInvalidValue;
 }
 
 template <class T>
-hipError_t dispatch_leaf(int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs, const void* a,
-                         double k0, double k1, void* V, hipStream_t st) {
-  switch (Ps) {
-    case 3: return leaf_r<3, T>(R, L, ic, xs, a, k0, k1, V, st);
-    case 4: return leaf_r<4, T>(R, L, ic, xs, a, k0, k1, V, st);
-    case 5: return leaf_r<5, T>(R, L, ic, xs, a, k0, k1, V, st);
-    case 6: return leaf_r<6, T>(R, L, ic, xs, a, k0, k1, V, st);
-  }
-  return hipErrorInvalidValue;
+hipError_t dispatch_leaf(int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+                         const void* a, double k0, double k1, void* V, hipStream_t st) {
+  return with_orders(Ps, Pa, [&]<int PS, int PA>() {
+    return with_columns<T>(R, [&]<int RR>() { return leaf_t<PS, PA, T, RR>(L, ic, xs, a, k0, k1, V, st); });
+  });
 }
 template <class T>
-hipError_t dispatch_prop(int Ps, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
-                         const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
-                         hipStream_t st) {
-  switch (Ps) {
-    case 3: return prop_r<3, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 4: return prop_r<4, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 5: return prop_r<5, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
-    case 6: return prop_r<6, T>(R, C, P, ic, G, k0, k1, Vc, Vp, st);
-  }
-  return hipErrorInvalidValue;
+hipError_t dispatch_prop(int Ps, int Pa, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+                         const PropGroups& G, double k0, double k1, const void* Vc, void* Vp, int spin_limit,
+                         unsigned* err, hipStream_t st) {
+  return with_orders(Ps, Pa, [&]<int PS, int PA>() {
+    return with_columns<T>(R, [&]<int RR>() {
+      return prop_t<PS, PA, T, RR>(C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st);
+    });
+  });
 }
 template <class T>
-hipError_t dispatch_targets(int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t dispatch_targets(int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                             const double* nrm, int64_t n, double k0, double k1, const void* V,
                             double2* out_s, hipStream_t st) {
-  switch (Ps) {
-    case 3: return targets_r<3, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 4: return targets_r<4, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 5: return targets_r<5, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-    case 6: return targets_r<6, T>(R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int PS, class T>
-hipError_t targets_tiles_t(const DevLevel& L, const InterpC& ic, const TargetTiles& TT, const double* xs,
-                           const double* nrm, double k0, double k1, const void* V, void* res, hipStream_t st) {
-  if (TT.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_targets_mfma<PS, T>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT, xs, nrm, k0,
-                     k1, static_cast<const T*>(V), static_cast<T*>(res));
-  return hipGetLastError();
+  return with_orders(Ps, Pa, [&]<int PS, int PA>() {
+    return with_columns<T>(R, [&]<int RR>() {
+      return targets_t<PS, PA, T, RR>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    });
+  });
 }
 template <class T>
-hipError_t dispatch_targets_tiles(int Ps, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
+hipError_t dispatch_targets_tiles(int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
                                   const double* xs, const double* nrm, double k0, double k1, const void* V,
                                   void* res, hipStream_t st) {
-  switch (Ps) {
-    case 3: return targets_tiles_t<3, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
-    case 4: return targets_tiles_t<4, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
-    case 5: return targets_tiles_t<5, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
-    case 6: return targets_tiles_t<6, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
-  }
-  return hipErrorInvalidValue;
+  return with_orders(Ps, Pa, [&]<int PS, int PA>() {
+    return targets_tiles_t<PS, PA, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
+  });
 }
 
 }  // namespace
 
-bool mfma_path_supported(int Ps, int Pa) { return Pa == 5 && Ps >= 3 && Ps <= 6; }
+bool mfma_path_supported(int Ps, int Pa) { return (Pa == 5 || Pa == 6) && Ps >= 3 && Ps <= 6; }
 
-int kslot_rows(int Ps) {
-  const int nab = 5 * Ps;
-  return 4 * (nab + (nab + 3) / 4);
+int kslot_rows(int Ps, int Pa) {
+  const int nab = Pa * Ps, tc = Pa - 4;
+  return 4 * (nab + (tc * nab + 3) / 4);
 }
 
-int max_batch_columns(bool fp32) { return fp32 ? 4 : 2; }
+int max_batch_columns(bool fp32, int Ps, int Pa) {
+  for (int R = fp32 ? 4 : 2; R > 1; R /= 2)
+    if (prop_lds_bytes(Ps, Pa, R, fp32 ? 4 : 8) <= kLdsLimit) return R;
+  return 1;
+}
 
 hipError_t mf_gather(bool fp32, int R, const double2* dens, const int64_t* perm, const double* w, int64_t n,
                      void* a, hipStream_t st) {
@@ -975,31 +1012,31 @@ hipError_t mf_gather(bool fp32, int R, const double2* dens, const int64_t* perm,
   return hipGetLastError();
 }
 
-hipError_t mf_leaf(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t mf_leaf(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                    const void* a, double k0, double k1, void* V, hipStream_t st) {
-  return fp32 ? dispatch_leaf<float>(Ps, R, L, ic, xs, a, k0, k1, V, st)
-              : dispatch_leaf<double>(Ps, R, L, ic, xs, a, k0, k1, V, st);
+  return fp32 ? dispatch_leaf<float>(Ps, Pa, R, L, ic, xs, a, k0, k1, V, st)
+              : dispatch_leaf<double>(Ps, Pa, R, L, ic, xs, a, k0, k1, V, st);
 }
 
-hipError_t mf_propagate(bool fp32, int Ps, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
-                        const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
-                        hipStream_t st) {
-  return fp32 ? dispatch_prop<float>(Ps, R, C, P, ic, G, k0, k1, Vc, Vp, st)
-              : dispatch_prop<double>(Ps, R, C, P, ic, G, k0, k1, Vc, Vp, st);
+hipError_t mf_propagate(bool fp32, int Ps, int Pa, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+                        const PropGroups& G, double k0, double k1, const void* Vc, void* Vp, int spin_limit,
+                        unsigned* err, hipStream_t st) {
+  return fp32 ? dispatch_prop<float>(Ps, Pa, R, C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st)
+              : dispatch_prop<double>(Ps, Pa, R, C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st);
 }
 
-hipError_t mf_targets(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                       const double* nrm, int64_t n, double k0, double k1, const void* V,
                       double2* out_s, hipStream_t st) {
-  return fp32 ? dispatch_targets<float>(Ps, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st)
-              : dispatch_targets<double>(Ps, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+  return fp32 ? dispatch_targets<float>(Ps, Pa, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st)
+              : dispatch_targets<double>(Ps, Pa, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
 }
 
-hipError_t mf_targets_tiles(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
+hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
                             const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
                             hipStream_t st) {
-  return fp32 ? dispatch_targets_tiles<float>(Ps, L, ic, TT, xs, nrm, k0, k1, V, res, st)
-              : dispatch_targets_tiles<double>(Ps, L, ic, TT, xs, nrm, k0, k1, V, res, st);
+  return fp32 ? dispatch_targets_tiles<float>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, st)
+              : dispatch_targets_tiles<double>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, st);
 }
 
 hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,

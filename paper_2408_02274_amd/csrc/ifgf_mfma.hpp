@@ -1,4 +1,4 @@
-// Matrix-core IFGF path: cone data in K-slot order (Pa = 5), FP32 or FP64.
+// Matrix-core IFGF path: cone data in K-slot order (Pa = 5 or 6), FP32 or FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,28 +32,30 @@ struct TargetTiles {
 };
 
 bool mfma_path_supported(int Ps, int Pa);
-int kslot_rows(int Ps);   // rows per cone in K-slot order
+int kslot_rows(int Ps, int Pa);   // rows per cone in K-slot order
 // Right-hand sides per pass: cone rows hold R groups of 32 reals, R in {1, 2, 4}
-// (FP32) or {1, 2} (FP64).
-int max_batch_columns(bool fp32);
+// (FP32) or {1, 2} (FP64), as far as the propagation's LDS allows.
+int max_batch_columns(bool fp32, int Ps, int Pa);
 
 // a: [n][R][16] weighted densities of dens[r][8][n], r < R
 hipError_t mf_gather(bool fp32, int R, const double2* dens, const int64_t* perm, const double* w, int64_t n,
                      void* a, hipStream_t st);
-hipError_t mf_leaf(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t mf_leaf(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                    const void* a, double k0, double k1, void* V, hipStream_t st);
-hipError_t mf_propagate(bool fp32, int Ps, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
-                        const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
-                        hipStream_t st);
+// spin_limit bounds the wait for the FP32 accumulator lock; a wavefront that
+// gives up skips its tile and sets bit 0 of *err (device word).
+hipError_t mf_propagate(bool fp32, int Ps, int Pa, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+                        const PropGroups& G, double k0, double k1, const void* Vc, void* Vp, int spin_limit,
+                        unsigned* err, hipStream_t st);
 // out_s: [R][n][28], accumulated
-hipError_t mf_targets(bool fp32, int Ps, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
                       const double* nrm, int64_t n, double k0, double k1, const void* V,
                       double2* out_s, hipStream_t st);
 
 // Target interpolation on the matrix cores (one right-hand side): per pair e
 // the 28 complex contributions into res [pairs][28] (complex in the cone
 // precision), then out_s[i] += sum of res over the pairs of target i.
-hipError_t mf_targets_tiles(bool fp32, int Ps, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
+hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
                             const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
                             hipStream_t st);
 hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,

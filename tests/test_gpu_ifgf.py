@@ -2,7 +2,12 @@
 
 Bar: the FP64 GPU IFGF equals the reference IFGF (O2) to 1e-10 relative L2
 (same algorithm, rounding order only), and stays within the IFGF error of
-the direct O(N^2) sum (O1).
+the direct O(N^2) sum (O1).  The O1 bars per output block (S sums, normal-
+derivative sums D) are the oracle's own interpolation errors at each order
+with some headroom: (3, 5) angular-only cones 5e-4..1.1e-3 (S) and
+2.0e-3..2.9e-3 (D); (5, 5) 1.3e-5..2.4e-5 (S) and 1.9e-4..2.5e-4 (D);
+(5, 6), the orders tol = 1e-4 selects, 6.5e-6..2.2e-5 (S) and 5.1e-5..7.4e-5
+(D), so there every block is within 1e-4.
 """
 import math
 
@@ -43,8 +48,14 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("order", [(3, 5), (5, 5)])
+O1_BARS = {(3, 5): (3e-3, 1e-2), (5, 5): (1e-4, 5e-4), (5, 6): (1e-4, 1e-4)}
+
+
+ORDER_CASES = [(c, o) for o in [(3, 5), (5, 5), (5, 6)] for c in CASES
+               if not (o == (5, 6) and c == "sphere_c1")]   # (5, 6) on sphere_c1: O2 is slow on the host
+
+
+@pytest.mark.parametrize("case,order", ORDER_CASES)
 def test_fp64_matches_reference_ifgf(case, order):
     s, ks = CASES[case]()
     rng = np.random.default_rng(21)
@@ -58,10 +69,30 @@ def test_fp64_matches_reference_ifgf(case, order):
         assert _rel(g[q, :8], o2[q, :8]) < 1e-10
         assert _rel(g[q, 8:], o2[q, 8:]) < 1e-10
     o1 = direct.regular_sums(s.x, s.normal, w, phi[0], ks)
-    bound = (3e-3, 1e-2) if order == (3, 5) else (2e-4, 2e-3)
+    bound = O1_BARS[order]
     for q in range(2):
         assert _rel(g[q, :8], o1[q, :8]) < bound[0]
         assert _rel(g[q, 8:], o1[q, 8:]) < bound[1]
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tol_1e4_holds_on_every_block(case, prec):
+    """tol = 1e-4 with the orders left to the plan: every output block (S and
+    D at both wavenumbers) within 1e-4 of the direct sum, FP64 and FP32."""
+    from paper_2408_02274_amd import IFGFPlan
+    s, ks = CASES[case]()
+    w = np.random.default_rng(21).uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 22)
+    _say(f"[gpu] ifgf tol=1e-4 {case} precision={prec}")
+    plan = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-4, precision=prec)
+    assert plan.counts()[2:4] == [5, 6]
+    g = plan.apply(torch.from_numpy(phi).to("cuda")).cpu().numpy()[0]
+    plan.close()
+    o1 = direct.regular_sums(s.x, s.normal, w, phi[0], ks)
+    errs = [_rel(g[q, :8], o1[q, :8]) for q in range(2)] + [_rel(g[q, 8:], o1[q, 8:]) for q in range(2)]
+    _say(f"    vs direct sum: S {errs[:2]}, D {errs[2:]}")
+    assert max(errs) < 1e-4
 
 
 def test_fp64_counting_free_cloud_and_nrhs():
@@ -95,8 +126,7 @@ def test_fp64_tiny_inputs_are_exact_direct_sums(npts):
     assert np.allclose(g, o1, rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("order", [(3, 5), (5, 5)])
+@pytest.mark.parametrize("case,order", ORDER_CASES)
 def test_fp32_cone_grids_close_to_reference(case, order):
     # FP32 cone values and interpolation (geometry in cone-centred FP32
     # coordinates): the rounding error is stated against the FP64 reference
@@ -144,9 +174,9 @@ def test_precision_switch_reproduces_fp64_plan():
     p64.close()
 
 
-@pytest.mark.parametrize("order", [(4, 6), (5, 7)])
+@pytest.mark.parametrize("order", [(4, 7), (5, 7)])
 def test_fp64_scalar_path_matches_reference_ifgf(order):
-    """Orders with Pa != 5 run the FP64 kernels with one thread per point
+    """Orders with Pa > 6 run the FP64 kernels with one thread per point
     (no matrix cores); same bar against the step-by-step reference IFGF."""
     s, ks = CASES["sphere864"]()
     rng = np.random.default_rng(23)
@@ -177,3 +207,52 @@ def test_literal_radial_refinement_matches_reference(prec):
     for q in range(2):
         assert _rel(g[q, :8], o2[q, :8]) < bar[0]
         assert _rel(g[q, 8:], o2[q, 8:]) < bar[1]
+
+
+@pytest.mark.parametrize("order", [(4, 6), (6, 6)])
+def test_pa6_orders_on_matrix_cores(order):
+    """Pa = 6 K-slot layout (two phi-nodes per (a, b) pair in the tail rows)
+    at other radial orders, FP64 (1e-10) and FP32 (2e-5 / 1e-4) against O2."""
+    from paper_2408_02274_amd import binding as B
+    s, ks = CASES["ellipsoid"]()
+    w = np.random.default_rng(27).uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 28)
+    Ps, Pa = order
+    o2 = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params(Ps=Ps, Pa=Pa)).apply(phi[0])
+    for prec, bar in ((B.IFGF_FP64, (1e-10, 1e-10)), (B.IFGF_FP32, (2e-5, 1e-4))):
+        _say(f"[gpu] ifgf ellipsoid Ps={Ps} Pa={Pa} precision={prec}")
+        g = _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa, precision=prec)[0]
+        for q in range(2):
+            assert _rel(g[q, :8], o2[q, :8]) < bar[0]
+            assert _rel(g[q, 8:], o2[q, 8:]) < bar[1]
+
+
+def test_lock_wait_give_up_is_reported():
+    """The FP32 propagation's bounded lock wait: with the bound set to 0 from
+    the host every locked add gives up (every kernel still ends normally) and
+    ifgf_check reports IFGF_EDEVICE; with the default bound the same plan
+    runs clean and equals the FP64 form to the FP32 bar."""
+    from paper_2408_02274_amd import IFGFPlan
+    from paper_2408_02274_amd import binding as B
+    s, ks = CASES["sphere_c1"]()
+    w = np.random.default_rng(29).uniform(0.5, 1.5, s.n)
+    d = torch.from_numpy(synth.complex_normal((1, 8, s.n), 30)).to("cuda")
+    _say("[gpu] lock give-up reporting sphere_c1 fp32")
+    p32 = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-3, Ps=5, Pa=5, precision=B.IFGF_FP32)
+    assert p32.counts()[1] >= 4        # at least one propagation launch
+    B.ifgf_set_lock_spin_limit(p32.handle, 0)
+    bad = p32.apply(d).cpu().numpy()
+    with pytest.raises(B.IFGFError) as ei:
+        B.ifgf_check(p32.handle)
+    assert ei.value.code == B.IFGF_EDEVICE
+    assert B.ifgf_check(p32.handle) == 0          # the check cleared the word
+    assert p32.stats()["device_error"] == 0
+    B.ifgf_set_lock_spin_limit(p32.handle, 1 << 22)
+    good = p32.apply(d).cpu().numpy()
+    assert B.ifgf_check(p32.handle) == 0
+    p64 = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-3, Ps=5, Pa=5)
+    ref = p64.apply(d).cpu().numpy()
+    p64.close()
+    p32.close()
+    assert _rel(good, ref) < 1e-4
+    assert _rel(bad, ref) > 1e-3                  # the skipped tiles are missing

@@ -36,7 +36,7 @@ def case_c1():
     return s, surf, nm_o
 
 
-@pytest.mark.parametrize("order", [(3, 5), (5, 5)])
+@pytest.mark.parametrize("order", [(3, 5), (5, 5), (5, 6)])
 def test_nmuller_apply_matches_oracle(case_c1, order):
     from paper_2408_02274_amd import NMullerOperator
     s, surf, nm_o = case_c1
@@ -59,7 +59,7 @@ def test_nmuller_apply_matches_oracle(case_c1, order):
         want = nm_o.apply(y[r], regular=ref.apply(phi))
         assert _rel(g[r][:, rows], want) < 1e-8
         direct_want = nm_o.apply(y[r])
-        bound = 2e-3 if order == (3, 5) else 2e-4
+        bound = 2e-3 if order == (3, 5) else 1e-4
         assert _rel(g[r][:, rows], direct_want) < bound
 
 
