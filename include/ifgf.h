@@ -256,6 +256,23 @@ typedef struct {
 int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, int use_x0, double rtol,
                   int maxit, int restart, ifgf_solve_info* info, void* stream);
 
+/* nmuller_solve for one right-hand side that allocates nothing, for callers
+ * that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments and result as nmuller_solve with nrhs = 1.
+ * The GMRES workspaces (Krylov basis [basis + 1][4n], the flexible basis
+ * [basis][4n] when a preconditioner is set, two vectors [4n] and the
+ * reduction partials; basis = restart if 0 < restart < maxit, else maxit)
+ * live in a static device array of 64 MiB that every GPU the library runs
+ * on holds until the process ends; a problem whose workspaces exceed it
+ * returns IFGF_EINVAL (e.g. 4n = 6,144 fits a basis of 600, 4n = 614,400 a
+ * basis of 5).  The operator's own buffers (built by nmuller_plan) are used
+ * as by nmuller_solve.  All calls on one GPU share the array: calls that
+ * overlap in time on one GPU race and must be serialised by the caller.
+ * Nothing in the array needs to start at zero (every workspace is written
+ * before it is read).  Synchronises the stream like nmuller_solve.        */
+int nmuller_solve_noalloc(nmuller_t nm, const void* rhs, void* y, int use_x0, double rtol, int maxit,
+                          int restart, ifgf_solve_info* info, void* stream);
+
 /* Unrestarted GMRES from y = 0 that also records iterates: after every
  * `stride`-th iteration k it writes x_k to X[j] and its residual
  * r_k = b - A x_k (from the Arnoldi relation, no extra matvec) to R[j],

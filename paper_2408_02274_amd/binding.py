@@ -88,6 +88,8 @@ def lib():
         L.nmuller_geometry.argtypes = [vp, ci, vp, i64]
         L.nmuller_corrections.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
         L.nmuller_solve.argtypes = [vp, vp, ci, vp, ci, dbl, ci, ci, C.POINTER(SolveInfo), vp]
+        L.nmuller_solve_noalloc.argtypes = [vp, vp, vp, ci, dbl, ci, ci, C.POINTER(SolveInfo), vp]
+        L.nmuller_solve_noalloc.restype = ci
         L.nmuller_solve.restype = ci
         L.nmuller_solve_trajectory.argtypes = [vp, vp, vp, dbl, ci, ci, vp, vp, ci, C.POINTER(ci),
                                                C.POINTER(SolveInfo), vp]
@@ -351,6 +353,16 @@ def nmuller_solve(nm, rhs, nrhs, y, use_x0=False, rtol=1e-4, maxit=500, restart=
                                float(rtol), int(maxit), int(restart), info, _stream_ptr(stream)),
            "nmuller_solve")
     return [_info_dict(i) for i in info]
+
+
+def nmuller_solve_noalloc(nm, rhs, y, use_x0=False, rtol=1e-4, maxit=500, restart=0, stream=None):
+    """One-RHS GMRES in the library's static scratch; rhs, y device [1][4][n]
+    complex128.  Returns the info dict."""
+    info = SolveInfo()
+    _check(lib().nmuller_solve_noalloc(nm, rhs.data_ptr(), y.data_ptr(), int(bool(use_x0)), float(rtol),
+                                       int(maxit), int(restart), C.byref(info), _stream_ptr(stream)),
+           "nmuller_solve_noalloc")
+    return _info_dict(info)
 
 
 def _info_dict(i):

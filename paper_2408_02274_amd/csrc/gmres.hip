@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <complex>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ifgf.h"
@@ -137,6 +138,36 @@ struct Solver {
           *coef = nullptr;
   int basis = 0;
 
+  // bytes of the workspaces below for a basis of nbasis vectors, each array
+  // starting on a 256-byte boundary
+  static size_t workspace_bytes(int64_t m, int nbasis, bool flexible) {
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t v = sizeof(double2) * (size_t)m;
+    return up(v * (nbasis + 1)) + (flexible ? up(v * nbasis) : 0) + 2 * up(v) +
+           up(sizeof(double2) * (size_t)kDotBlocks * (nbasis + 2)) + 2 * up(sizeof(double2) * (size_t)(nbasis + 2));
+  }
+  // the same workspaces carved from caller-provided device memory (no allocation)
+  int init_in(char* base, size_t cap, int nbasis, bool flexible) {
+    if (workspace_bytes(m, nbasis, flexible) > cap)
+      return set_error(IFGF_EINVAL, "GMRES workspace of " + std::to_string(workspace_bytes(m, nbasis, flexible)) +
+                                        " bytes exceeds the " + std::to_string(cap) +
+                                        "-byte static scratch; lower restart or the problem size");
+    basis = nbasis;
+    auto take = [&](size_t bytes) {
+      double2* p = reinterpret_cast<double2*>(base);
+      base += (bytes + 255) & ~(size_t)255;
+      return p;
+    };
+    const size_t v = sizeof(double2) * (size_t)m;
+    V = take(v * (basis + 1));
+    if (flexible) Z = take(v * basis);
+    w = take(v);
+    tmp = take(v);
+    part = take(sizeof(double2) * (size_t)kDotBlocks * (basis + 2));
+    h = take(sizeof(double2) * (size_t)(basis + 2));
+    coef = take(sizeof(double2) * (size_t)(basis + 2));
+    return 0;
+  }
   int init(int nbasis, bool flexible) {
     basis = nbasis;
     V = static_cast<double2*>(ar.alloc(sizeof(double2) * (size_t)m * (basis + 1)));
@@ -465,6 +496,31 @@ int run_one(Fgmres& G, nmuller_t nm, int64_t m, hipStream_t st) {
   return rc;
 }
 
+// Static scratch of nmuller_solve_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (its
+// host-side name is not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+int scratch_ptr(char** out) {
+  static std::mutex mu;
+  static char* ptrs[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_hip_error(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return set_error(IFGF_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+      return set_hip_error(e, "hipGetSymbolAddress(scratch)");
+    ptrs[dev] = static_cast<char*>(p);
+  }
+  *out = ptrs[dev];
+  return 0;
+}
+
 int solver_size(nmuller_t nm, int64_t* n) {
   int64_t c[1];
   int rc = ifgf_plan_counts(nmuller_ifgf(nm), c, 1);
@@ -559,6 +615,32 @@ extern "C" int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, i
   // a device-side failure of any apply makes the whole solve suspect
   if ((rc = ifgf_check(nmuller_ifgf(nm), stream, nullptr))) return rc;
   return status;
+}
+
+extern "C" int nmuller_solve_noalloc(nmuller_t nm, const void* rhs, void* y, int use_x0, double rtol, int maxit,
+                                     int restart, ifgf_solve_info* info, void* stream) {
+  clear_error();
+  if (!nm || !rhs || !y) return set_error(IFGF_EINVAL, "null argument");
+  if (!(rtol > 0.0) || maxit < 1) return set_error(IFGF_EINVAL, "need rtol > 0 and maxit >= 1");
+  int64_t n = 0;
+  int rc = solver_size(nm, &n);
+  if (rc) return rc;
+  char* base = nullptr;
+  if ((rc = scratch_ptr(&base))) return rc;
+  const bool precond = nmuller_precond(nm) != nullptr;
+  Solver S;
+  S.nm = nm;
+  S.m = 4 * n;
+  S.st = static_cast<hipStream_t>(stream);
+  const int basis = (restart > 0 && restart < maxit) ? restart : maxit;
+  if ((rc = S.init_in(base, kScratchBytes, basis, precond))) return rc;
+  double2* x = static_cast<double2*>(y);
+  if (!use_x0) hipLaunchKernelGGL(k_fill, dim3(nblk(S.m)), dim3(kBS), 0, S.st, x, S.m);
+  Fgmres G(S, static_cast<const double2*>(rhs), x, rtol, maxit, precond, nullptr, true);
+  if ((rc = run_one(G, nm, S.m, S.st))) return rc;
+  if (info) *info = G.info();
+  if ((rc = ifgf_check(nmuller_ifgf(nm), stream, nullptr))) return rc;
+  return G.info().converged ? IFGF_OK : IFGF_WNOCONV;
 }
 
 extern "C" int nmuller_solve_trajectory(nmuller_t nm, const void* rhs, void* y, double rtol, int maxit, int stride,

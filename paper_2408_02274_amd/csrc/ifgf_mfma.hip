@@ -10,12 +10,21 @@
 // with nab = Pa Ps, tc = Pa - 4 and KS = nab + ceil(tc nab / 4):
 //   c < 4  : row 4 * ab + c                      (ab = Pa a + b)
 //   c >= 4 : row 4 * nab + tc * ab + (c - 4)
-// remaining rows are zero padding.  A row holds R groups of 32 reals, one
-// group per right-hand side of the batch: the real parts of the 16 complex
-// columns (column = 8 * kernel + density) then their imaginary parts.  With
-// this order the MFMA lane group g = lane / 16 supplies the phi-node c = g in
-// the first nab k-steps and c = 4 + g mod tc in the others, so the
-// interpolation weight of a lane is one product of per-point Lagrange factors.
+// remaining rows (up to an even number KS2 of 4-row k-steps) are zero
+// padding.  A row holds R groups of 32 reals, one group per right-hand side of
+// the batch: the real parts of the 16 complex columns (column = 8 * kernel +
+// density) then their imaginary parts.  With this order the MFMA lane group
+// g = lane / 16 supplies the phi-node c = g in the first nab k-steps and
+// c = 4 + g mod tc in the others, so the interpolation weight of a lane is
+// one product of per-point Lagrange factors.
+//
+// In memory the (row, column) values of a cone are stored in the order the
+// matrix cores consume them (see kofs): for each pair of k-steps and each
+// right-hand side, lane l = 16 g + c of a wavefront finds the four B operands
+// it needs -- (row 4 j + g, column c), (row 4 j + g, column 16 + c) for
+// j = 2 jp and j = 2 jp + 1 -- in four consecutive reals, so one 16-byte
+// (FP32) load per lane feeds four MFMAs and a wavefront reads 1 KB of
+// contiguous memory per load.
 //
 // The interpolant is the tensor Chebyshev interpolant of Sec. III-F in
 // Lagrange form on the same nodes (identical polynomial).  Geometry is
@@ -168,16 +177,41 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
 template <int PS, int PA> struct KSlot {
   static constexpr int NAB = PS * PA;               // (radial, polar) node pairs
   static constexpr int TC = PA - 4;                 // phi-nodes past the first four
-  static constexpr int KS = NAB + (TC * NAB + 3) / 4;
-  static constexpr int K = 4 * KS;
+  static constexpr int KS = NAB + (TC * NAB + 3) / 4;   // k-steps that carry nodes
+  static constexpr int KS2 = KS + (KS & 1);         // k-steps stored (even)
+  static constexpr int K = 4 * KS2;                 // rows stored per cone
   static constexpr int NPTS = NAB * PA;
 };
 
+// Offset of (row, column) within one cone of R right-hand sides (32 R reals
+// per row) in matrix-core consumption order: k-step pair jp = row / 8,
+// right-hand side r = column / 32, lane 16 (row mod 4) + column mod 16,
+// then (k-step parity, real/imaginary half).
+template <int R>
+__device__ __forceinline__ int kofs(int row, int col) {
+  const int j = row >> 2, g = row & 3;
+  const int r = col >> 5, h = (col >> 4) & 1, c = col & 15;
+  return (((j >> 1) * R + r) * 64 + 16 * g + c) * 4 + 2 * (j & 1) + h;
+}
+
+template <class T> struct Vec4;
+template <> struct Vec4<float> { using type = f4v; };
+template <> struct Vec4<double> { using type = d4v; };
+
 // LDS of the propagation kernel: accumulator, per-wavefront geometry records
-// (4 x 64 lanes x (10 + 2 Pa) values), parent-point geometry, lock
-constexpr int64_t prop_lds_bytes(int Ps, int Pa, int R, int elem) {
-  return (int64_t)Ps * Pa * Pa * (32 * R + 1) * elem + 4 * 64 * (10 + 2 * Pa) * elem +
+// (4 wavefronts x 16 rows x tb tiles x (10 + 2 Pa) values), parent-point
+// geometry, lock
+constexpr int64_t prop_lds_bytes_tb(int Ps, int Pa, int R, int elem, int tb) {
+  return (int64_t)Ps * Pa * Pa * (32 * R + 1) * elem + 4 * 16 * tb * (10 + 2 * Pa) * elem +
          (int64_t)Ps * Pa * Pa * 4 * elem + 4;
+}
+// Tiles a wavefront prepares per geometry phase: 4, or 2 where that keeps an
+// FP64 block within 80 KB of LDS (two blocks per compute unit).
+constexpr int prop_tiles_per_batch(int Ps, int Pa, int R, int elem) {
+  return (elem == 8 && prop_lds_bytes_tb(Ps, Pa, R, elem, 4) > 80 * 1024) ? 2 : 4;
+}
+constexpr int64_t prop_lds_bytes(int Ps, int Pa, int R, int elem) {
+  return prop_lds_bytes_tb(Ps, Pa, R, elem, prop_tiles_per_batch(Ps, Pa, R, elem));
 }
 constexpr int64_t kLdsLimit = 160 * 1024;
 
@@ -222,11 +256,15 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
   int64_t q = t / (K * R);
   int row = (int)((t / R) % K);
   const int r = (int)(t % R);
-  T* o = V + t * 32;
+  // column c (real part) and 16 + c (imaginary part) sit side by side
+  T* o = V + q * (int64_t)K * 32 * R + kofs<R>(row, 32 * r);
   int p = point_of_row<PA>(row, NAB);
   if (p < 0) {
 #pragma unroll
-    for (int c = 0; c < 32; ++c) o[c] = (T)0;
+    for (int c = 0; c < 16; ++c) {
+      o[4 * c] = (T)0;
+      o[4 * c + 1] = (T)0;
+    }
     return;
   }
   int32_t b = L.slot_box[q];
@@ -260,15 +298,19 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
     }
   }
 #pragma unroll
-  for (int m = 0; m < 32; ++m) o[m] = acc[m];
+  for (int c = 0; c < 16; ++c) {
+    o[4 * c] = acc[c];
+    o[4 * c + 1] = acc[16 + c];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // propagation: one workgroup per parent cone slot, 4 wavefronts.  The tiles
 // (16 parent points of one child cone) are dealt round-robin to the
-// wavefronts.  A wavefront takes its tiles four at a time: one lane per point
-// evaluates the child-cone coordinates, Lagrange factors and re-centring
-// factor of its point into wave-private LDS, then the four MFMA tiles run.
+// wavefronts.  A wavefront takes its tiles TB (4, or 2 for large FP64 cones)
+// at a time: one lane per point evaluates the child-cone coordinates,
+// Lagrange factors and re-centring factor of its point into wave-private LDS,
+// then the TB MFMA tiles run.
 template <int PS, int PA, class T, int R>
 __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, InterpC ic, PropGroups G,
                                                    double k0, double k1, const T* __restrict__ Vc,
@@ -283,8 +325,9 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   // re-centring factors [OF, OF + 4)
   constexpr int OT = 6, OP = OT + PA, OF = OP + PA, GW = OF + 4;
   constexpr int W = 32 * R;             // reals per cone row
+  constexpr int TB = prop_tiles_per_batch(PS, PA, R, sizeof(T));
   __shared__ T acc[NPTS][W + 1];
-  __shared__ T gbuf[4][64][GW];         // per wavefront: 4 tiles x 16 rows
+  __shared__ T gbuf[4][16 * TB][GW];    // per wavefront: TB tiles x 16 rows
   __shared__ T geo[NPTS][4];            // parent points about the parent centre, and r_p
   __shared__ int acc_lock;              // held by the wavefront adding a tile into acc
   const int64_t q = xcd_remap(blockIdx.x, gridDim.x);
@@ -310,33 +353,33 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   const T two_ds = (T)(2.0 * C.ns / kEtaD), two_da = (T)(2.0 * C.na / kPiD);
   T(*gb)[GW] = gbuf[wave];
   const int64_t t_beg = G.toff[q], t_end = G.toff[q + 1];
-  // this wavefront owns tiles t_beg + wave + 4 i, taken four at a time; the
-  // records of the next four are fetched while the current ones run
-  // rb / rn: the four records, wave-uniform; mine / mine_n: this lane's own
-  // record for the geometry phase (tile gl of the four)
-  int4 rb[4], rn[4], mine, mine_n;
+  // this wavefront owns tiles t_beg + wave + 4 i, taken TB at a time; the
+  // records of the next TB are fetched while the current ones run
+  // rb / rn: the TB records, wave-uniform; mine / mine_n: this lane's own
+  // record for the geometry phase (tile gl of the TB)
+  int4 rb[TB], rn[TB], mine, mine_n;
   int nb = 0;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < TB; ++b) {
     const int64_t tl = t_beg + wave + 4 * b;
     rb[b] = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
     nb += tl < t_end ? 1 : 0;
   }
   {
     const int64_t tl = t_beg + wave + 4 * gl;
-    mine = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
+    mine = (gl < TB && tl < t_end) ? G.rec[tl] : make_int4(0, 0, 0, 0);
   }
-  for (int64_t tb = t_beg + wave; tb < t_end; tb += 16) {
+  for (int64_t tb = t_beg + wave; tb < t_end; tb += 4 * TB) {
     int nn = 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t tl = tb + 16 + 4 * b;
+    for (int b = 0; b < TB; ++b) {
+      const int64_t tl = tb + 4 * TB + 4 * b;
       rn[b] = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
       nn += tl < t_end ? 1 : 0;
     }
     {
-      const int64_t tl = tb + 16 + 4 * gl;
-      mine_n = tl < t_end ? G.rec[tl] : make_int4(0, 0, 0, 0);
+      const int64_t tl = tb + 4 * TB + 4 * gl;
+      mine_n = (gl < TB && tl < t_end) ? G.rec[tl] : make_int4(0, 0, 0, 0);
     }
     // geometry: lane -> (tile lane / 16, row lane % 16); the lane keeps its
     // parent point index for the epilogues, which read it across lanes
@@ -395,10 +438,10 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < TB; ++b) {
       if (b >= nb) break;
       const int cnt = rb[b].w & 31;
-      const T* Vs = Vc + (int64_t)rb[b].x * K * W + gl * W;
+      const T* Vs = Vc + (int64_t)rb[b].x * K * W + 4 * lane;
       const T* me = gb[16 * b + r16];
       T Ls[PS], Lt[PA];
 #pragma unroll
@@ -408,40 +451,54 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       const T lpg = me[OP + gl];
       // phi-node of this lane in the tail k-steps: 4 + gl mod tc
       const T lp4 = me[OP + 4 + (TC == 1 ? 0 : (gl & 1))];
-      T st[NAB];
+      // st(ab) = Ls[a] Lt[b]: tabulated in registers, or formed per k-step
+      // for large FP64 cones (the table's registers would cost occupancy)
+      constexpr bool kTab = sizeof(T) == 4 || NAB <= 25;
+      T st[kTab ? NAB : 1];
+      if constexpr (kTab) {
 #pragma unroll
-      for (int ab = 0; ab < NAB; ++ab) st[ab] = Ls[ab / PA] * Lt[ab % PA];
+        for (int ab = 0; ab < NAB; ++ab) st[ab] = Ls[ab / PA] * Lt[ab % PA];
+      }
+      auto stv = [&](int ab) -> T {
+        if constexpr (kTab) return st[ab];
+        else return Ls[ab / PA] * Lt[ab % PA];
+      };
       typename MF<T>::acc c0[R], c1[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         c0[r] = typename MF<T>::acc{0, 0, 0, 0};
         c1[r] = typename MF<T>::acc{0, 0, 0, 0};
       }
+      typename Vec4<T>::type bv[R];
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
+        if ((j & 1) == 0) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            bv[r] = *reinterpret_cast<const typename Vec4<T>::type*>(Vs + (int64_t)((j >> 1) * R + r) * 256);
+        }
         T av;
         if (j < NAB) {
-          av = st[j] * lpg;
+          av = stv(j) * lpg;
         } else if constexpr (TC == 1) {
           // slot 4 j + gl holds phi-node 4 of (a, b) pair m = 4 (j - NAB) + gl
           const int m0 = 4 * (j - NAB);
-          T sel = (m0 < NAB) ? st[m0 < NAB ? m0 : 0] : (T)0;
-          sel = (gl == 1) ? ((m0 + 1 < NAB) ? st[m0 + 1 < NAB ? m0 + 1 : 0] : (T)0) : sel;
-          sel = (gl == 2) ? ((m0 + 2 < NAB) ? st[m0 + 2 < NAB ? m0 + 2 : 0] : (T)0) : sel;
-          sel = (gl == 3) ? ((m0 + 3 < NAB) ? st[m0 + 3 < NAB ? m0 + 3 : 0] : (T)0) : sel;
+          T sel = (m0 < NAB) ? stv(m0 < NAB ? m0 : 0) : (T)0;
+          sel = (gl == 1) ? ((m0 + 1 < NAB) ? stv(m0 + 1 < NAB ? m0 + 1 : 0) : (T)0) : sel;
+          sel = (gl == 2) ? ((m0 + 2 < NAB) ? stv(m0 + 2 < NAB ? m0 + 2 : 0) : (T)0) : sel;
+          sel = (gl == 3) ? ((m0 + 3 < NAB) ? stv(m0 + 3 < NAB ? m0 + 3 : 0) : (T)0) : sel;
           av = sel * lp4;
         } else {
           // slot 4 j + gl holds phi-node 4 + (gl & 1) of pair m = 2 (j - NAB) + gl / 2
           const int m0 = 2 * (j - NAB);
-          T sel = (m0 < NAB) ? st[m0 < NAB ? m0 : 0] : (T)0;
-          sel = (gl >= 2) ? ((m0 + 1 < NAB) ? st[m0 + 1 < NAB ? m0 + 1 : 0] : (T)0) : sel;
+          T sel = (m0 < NAB) ? stv(m0 < NAB ? m0 : 0) : (T)0;
+          sel = (gl >= 2) ? ((m0 + 1 < NAB) ? stv(m0 + 1 < NAB ? m0 + 1 : 0) : (T)0) : sel;
           av = sel * lp4;
         }
-        const T* vrow = Vs + (int64_t)(4 * j) * W;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          c0[r] = MF<T>::mma(av, vrow[32 * r + r16], c0[r]);
-          c1[r] = MF<T>::mma(av, vrow[32 * r + 16 + r16], c1[r]);
+          c0[r] = MF<T>::mma(av, (j & 1) ? bv[r][2] : bv[r][0], c0[r]);
+          c1[r] = MF<T>::mma(av, (j & 1) ? bv[r][3] : bv[r][1], c1[r]);
         }
       }
       // lane holds rows MF::row(lane, e), complex column r16 (kernel r16 / 8)
@@ -534,14 +591,18 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rb[b] = rn[b];
+    for (int b = 0; b < TB; ++b) rb[b] = rn[b];
     mine = mine_n;
     nb = nn;
   }
   __syncthreads();
+  // contiguous stores in consumption order: offset i -> (row, column)
   T* out = Vp + q * (int64_t)K * W;
   for (int i = tid; i < K * W; i += 256) {
-    const int row = i / W, col = i % W;
+    const int h = i & 1, jo = (i >> 1) & 1, li = (i >> 2) & 63, blk = i >> 8;
+    const int r = blk % R, jp = blk / R;
+    const int row = 4 * (2 * jp + jo) + (li >> 4);
+    const int col = 32 * r + 16 * h + (li & 15);
     const int p = point_of_row<PA>(row, NAB);
     out[i] = p >= 0 ? acc[p][col] : (T)0;
   }
@@ -609,7 +670,7 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
     for (int m = 0; m < 16; ++m) F[m] = (T)0;
 #pragma unroll
     for (int m = 0; m < 12; ++m) FD[m] = (T)0;
-    const T* Vs = V + (int64_t)slot * K * 32 * R + 32 * rr + 8 * q;
+    const T* Vs = V + (int64_t)slot * K * 32 * R;
     // radial index a runs in a rolled loop; Ls/dLs rotate so indices stay static
 #pragma unroll 1
     for (int a = 0; a < PS; ++a) {
@@ -641,16 +702,17 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
             Lp[PA - 1] = l0;
             dLp[PA - 1] = d0;
           }
-          const T* vr = Vs + (int64_t)row * 32 * R;
+          // column 8 q + m: real part at vr[4 m], imaginary part at vr[4 m + 1]
+          const T* vr = Vs + kofs<R>(row, 32 * rr + 8 * q);
 #pragma unroll
           for (int m = 0; m < 8; ++m) {
-            F[m] += w * vr[m];
-            F[8 + m] += w * vr[16 + m];
+            F[m] += w * vr[4 * m];
+            F[8 + m] += w * vr[4 * m + 1];
           }
 #pragma unroll
           for (int m = 0; m < 6; ++m) {
-            FD[m] += wd * vr[m];
-            FD[6 + m] += wd * vr[16 + m];
+            FD[m] += wd * vr[4 * m];
+            FD[6 + m] += wd * vr[4 * m + 1];
           }
         }
       }
@@ -801,9 +863,11 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   const int ct4 = 4 + (TC == 1 ? 0 : (gl & 1));
   const T g1 = kv * me[OLP + ct4] + kd * me[OPD + ct4], g2 = kd * me[OLP + ct4];
   typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-  const T* Vs = V + (int64_t)slot * K * 32 + gl * 32;
+  const T* Vs = V + (int64_t)slot * K * 32 + 4 * lane;
+  typename Vec4<T>::type bv;
 #pragma unroll
   for (int j = 0; j < KS; ++j) {
+    if ((j & 1) == 0) bv = *reinterpret_cast<const typename Vec4<T>::type*>(Vs + (int64_t)(j >> 1) * 256);
     T av;
     if (j < NAB) {
       av = Ltv[j % PA] * U[j / PA] + Tdv[j % PA] * W[j / PA];   // (a, b) = j, phi-node gl
@@ -816,9 +880,8 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
         av = (T)0;
       }
     }
-    const T* vrow = Vs + (int64_t)(4 * j) * 32;
-    c0 = MF<T>::mma(av, vrow[r16], c0);
-    c1 = MF<T>::mma(av, vrow[16 + r16], c1);
+    c0 = MF<T>::mma(av, (j & 1) ? bv[2] : bv[0], c0);
+    c1 = MF<T>::mma(av, (j & 1) ? bv[3] : bv[1], c1);
   }
   T(*ob)[33] = outb[wave];
 #pragma unroll
@@ -991,7 +1054,8 @@ bool mfma_path_supported(int Ps, int Pa) { return (Pa == 5 || Pa == 6) && Ps >= 
 
 int kslot_rows(int Ps, int Pa) {
   const int nab = Pa * Ps, tc = Pa - 4;
-  return 4 * (nab + (tc * nab + 3) / 4);
+  const int ks = nab + (tc * nab + 3) / 4;
+  return 4 * (ks + (ks & 1));
 }
 
 int max_batch_columns(bool fp32, int Ps, int Pa) {
