@@ -214,6 +214,9 @@ constexpr int64_t prop_lds_bytes(int Ps, int Pa, int R, int elem) {
   return prop_lds_bytes_tb(Ps, Pa, R, elem, prop_tiles_per_batch(Ps, Pa, R, elem));
 }
 constexpr int64_t kLdsLimit = 160 * 1024;
+// pairs of k-steps whose B operands a propagation wavefront keeps in flight
+// (FP64 operands take twice the registers)
+constexpr int prop_prefetch(int elem) { return elem == 4 ? 6 : 3; }
 
 template <int PA>
 __device__ __forceinline__ int point_of_row(int row, int nab) {
@@ -319,6 +322,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   constexpr int NAB = KSlot<PS, PA>::NAB;
   constexpr int TC = KSlot<PS, PA>::TC;
   constexpr int KS = KSlot<PS, PA>::KS;
+  constexpr int KS2 = KSlot<PS, PA>::KS2;
   constexpr int K = KSlot<PS, PA>::K;
   constexpr int NPTS = KSlot<PS, PA>::NPTS;
   // per-lane geometry record: Ls [0, PS), Lt [OT, OT + PA), Lp [OP, OP + PA),
@@ -369,6 +373,24 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
     const int64_t tl = t_beg + wave + 4 * gl;
     mine = (gl < TB && tl < t_end) ? G.rec[tl] : make_int4(0, 0, 0, 0);
   }
+  // B operands: one 16-byte (FP32) load per lane and right-hand side per
+  // pair of k-steps, issued PD - 1 pairs ahead of its use into a ring of
+  // registers; a scheduling barrier after each pair keeps the compiler from
+  // sinking the loads next to their use (an L2 hit takes far longer than the
+  // MFMAs of one pair).  The first pairs of a tile are requested before the
+  // epilogue of the tile before it.
+  using V4 = typename Vec4<T>::type;
+  constexpr int NP = KS2 / 2;
+  constexpr int PD = prop_prefetch(sizeof(T));
+  V4 ring[PD][R];
+  auto first_pairs = [&](int32_t child_slot) {
+    const T* vs = Vc + (int64_t)child_slot * K * W + 4 * lane;
+#pragma unroll
+    for (int i = 0; i < PD - 1 && i < NP; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) ring[i][r] = *reinterpret_cast<const V4*>(vs + (int64_t)(i * R + r) * 256);
+  };
+  if (nb > 0) first_pairs(rb[0].x);
   for (int64_t tb = t_beg + wave; tb < t_end; tb += 4 * TB) {
     int nn = 0;
 #pragma unroll
@@ -469,13 +491,13 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         c0[r] = typename MF<T>::acc{0, 0, 0, 0};
         c1[r] = typename MF<T>::acc{0, 0, 0, 0};
       }
-      typename Vec4<T>::type bv[R];
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
-        if ((j & 1) == 0) {
+        const int jp = j >> 1;
+        if ((j & 1) == 0 && jp + PD - 1 < NP) {
 #pragma unroll
           for (int r = 0; r < R; ++r)
-            bv[r] = *reinterpret_cast<const typename Vec4<T>::type*>(Vs + (int64_t)((j >> 1) * R + r) * 256);
+            ring[(jp + PD - 1) % PD][r] = *reinterpret_cast<const V4*>(Vs + (int64_t)((jp + PD - 1) * R + r) * 256);
         }
         T av;
         if (j < NAB) {
@@ -497,10 +519,16 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          c0[r] = MF<T>::mma(av, (j & 1) ? bv[r][2] : bv[r][0], c0[r]);
-          c1[r] = MF<T>::mma(av, (j & 1) ? bv[r][3] : bv[r][1], c1[r]);
+          const V4& b4 = ring[jp % PD][r];
+          c0[r] = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0[r]);
+          c1[r] = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1[r]);
         }
+        if (j & 1) __builtin_amdgcn_sched_barrier(0);
       }
+      // the next tile (of this batch, else the first of the next batch)
+      if (b + 1 < nb) first_pairs(rb[b + 1 < TB ? b + 1 : 0].x);
+      else if (nn > 0) first_pairs(rn[0].x);
+      __builtin_amdgcn_sched_barrier(0);
       // lane holds rows MF::row(lane, e), complex column r16 (kernel r16 / 8)
       const int qq = r16 >> 3;
       if constexpr (sizeof(T) == 4) {
@@ -864,10 +892,19 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   const T g1 = kv * me[OLP + ct4] + kd * me[OPD + ct4], g2 = kd * me[OLP + ct4];
   typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
   const T* Vs = V + (int64_t)slot * K * 32 + 4 * lane;
-  typename Vec4<T>::type bv;
+  // B operands of a pair of k-steps are requested PD - 1 pairs ahead of
+  // their use (see the propagation kernel)
+  using V4 = typename Vec4<T>::type;
+  constexpr int NP = KSlot<PS, PA>::KS2 / 2;
+  constexpr int PD = prop_prefetch(sizeof(T));
+  V4 ring[PD];
+#pragma unroll
+  for (int i = 0; i < PD - 1 && i < NP; ++i) ring[i] = *reinterpret_cast<const V4*>(Vs + (int64_t)i * 256);
 #pragma unroll
   for (int j = 0; j < KS; ++j) {
-    if ((j & 1) == 0) bv = *reinterpret_cast<const typename Vec4<T>::type*>(Vs + (int64_t)(j >> 1) * 256);
+    const int jp = j >> 1;
+    if ((j & 1) == 0 && jp + PD - 1 < NP)
+      ring[(jp + PD - 1) % PD] = *reinterpret_cast<const V4*>(Vs + (int64_t)(jp + PD - 1) * 256);
     T av;
     if (j < NAB) {
       av = Ltv[j % PA] * U[j / PA] + Tdv[j % PA] * W[j / PA];   // (a, b) = j, phi-node gl
@@ -880,8 +917,10 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
         av = (T)0;
       }
     }
-    c0 = MF<T>::mma(av, (j & 1) ? bv[2] : bv[0], c0);
-    c1 = MF<T>::mma(av, (j & 1) ? bv[3] : bv[1], c1);
+    const V4& b4 = ring[jp % PD];
+    c0 = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0);
+    c1 = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1);
+    if (j & 1) __builtin_amdgcn_sched_barrier(0);
   }
   T(*ob)[33] = outb[wave];
 #pragma unroll
