@@ -89,24 +89,49 @@ def traffic_per_launch(kernel, precision, points, Ps, Pa):
         return None
 
 
-def cpu_baseline(surface, ks, w, sample_rows, seed=2):
-    """Time the oracle's O(N^2) regular sums on a sample of target rows."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample(args, npatch, log, mie_solution=None):
+    """O1 (direct sums, singular corrections, assembly) on the nodes of
+    `npatch` patches drawn from seed 2, run by the oracle's own program over a
+    process pool of the host cores (one BLAS thread per worker); optionally the
+    Mie error of a solution.  Returns the oracle's arrays and timings."""
+    import tempfile
+    import subprocess
     import numpy as np
-    from threadpoolctl import threadpool_info
-    import synth
-    from oracle import direct
-    phi = synth.complex_normal((8, surface.n), seed)
-    rows = np.arange(sample_rows)
+    nproc = min(16, os.cpu_count() or 1)
+    out = os.path.join(tempfile.mkdtemp(), "o1.npz")
+    cmd = [sys.executable, "-m", "oracle.sample", "--npf", str(args.npf), "--nc", str(args.nc),
+           "--radius", str(args.radius), "--npatch", str(npatch), "--nproc", str(nproc), "--out", out]
+    if mie_solution is not None:
+        cmd += ["--mie-solution", mie_solution]
     t0 = time.perf_counter()
-    direct.regular_sums(surface.x, surface.normal, w, phi, ks, targets=rows, block=64)
-    dt = time.perf_counter() - t0
-    per_matvec = dt * surface.n / sample_rows
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle O1 direct regular sums (S and n.grad S, 8 densities x 2 wavenumbers) "
-                      f"for {sample_rows} of {surface.n} target rows took {dt:.1f} s; extrapolated "
-                      f"x{surface.n / sample_rows:.0f} to one matvec (the corrections and assembly, "
-                      f"O(N), are left out in the oracle's favour)"}
+    subprocess.run(cmd, cwd=ROOT, check=True, timeout=1200)
+    log(f"oracle sample ({npatch} patches, {nproc} processes) in {time.perf_counter() - t0:.1f} s")
+    return dict(np.load(out))
+
+
+def o2_config1_seconds(Ps, Pa):
+    """Wall time of one reference-IFGF evaluation (O2, single process) on the
+    1,536-point unit sphere (24 patches x 8 x 8 nodes, k_int = 3 pi, k_ext = 2 pi)
+    at the given orders: context for the CPU cost of the method itself."""
+    import synth
+    from oracle import ifgf_ref
+    s = synth.cube_sphere(2, 8, 1.0)
+    import numpy as np
+    w = np.full(s.n, 4 * math.pi / s.n)
+    phi = synth.complex_normal((8, s.n), 1)
+    t0 = time.perf_counter()
+    ifgf_ref.ReferenceIFGF(s.x, s.normal, w, (3 * math.pi, 2 * math.pi), ifgf_ref.Params(Ps=Ps, Pa=Pa)).apply(phi)
+    return time.perf_counter() - t0
 
 
 def batching(log, reps=5):
@@ -269,7 +294,8 @@ def main():
     ap.add_argument("--npf", type=int, default=16, help="patches per cube face edge")
     ap.add_argument("--nc", type=int, default=10, help="Chebyshev nodes per patch direction")
     ap.add_argument("--radius", type=float, default=5.0)
-    ap.add_argument("--cpu-rows", type=int, default=1536)
+    ap.add_argument("--oracle-patches", type=int, default=41,
+                    help="patches whose nodes the oracle evaluates (41 x 100 points at the default size)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-fp64-gmres", action="store_true", help="skip the FP64-form GMRES solve")
@@ -354,6 +380,19 @@ def main():
     kern = kernel_table(st, args.steps, npts)
     out_main = out.clone()
 
+    # IFGF sums of seeded densities (phi seed 3) in the working form: compared
+    # with the oracle's direct sums on sampled rows at the end
+    def ifgf_sums():
+        phi = torch.from_numpy(synth.complex_normal((1, 8, surf.n), 3)).to("cuda")
+        sd = torch.empty((1, 2, 14, surf.n), dtype=torch.complex128, device="cuda")
+        B.ifgf_apply(ih, phi, 1, sd)
+        torch.cuda.synchronize()
+        return sd.cpu().numpy()[0]
+
+    gpu_forms = {}
+    if not args.ifgf_only and args.nrhs == 1:
+        gpu_forms[args.precision] = {"SD": ifgf_sums(), "Ay": out_main.cpu().numpy()[0]}
+
     # the plain FP64 form of the same operator, and the mixed form's deviation from it
     fp64_form = None
     if fp32 and not args.no_fp64_form:
@@ -361,6 +400,8 @@ def main():
         el64, st64 = timed_steps(max(1, min(args.steps, 3)), 1)
         n64 = max(1, min(args.steps, 3))
         dev = float(torch.linalg.norm(out_main - out) / torch.linalg.norm(out))
+        if "fp32" in gpu_forms:
+            gpu_forms["fp64"] = {"SD": ifgf_sums(), "Ay": out.cpu().numpy()[0]}
         B.ifgf_set_precision(ih, B.IFGF_FP32)
         k64 = kernel_table(st64, n64, npts)
         fp64_form = {"matvecs_per_s": n64 * args.nrhs / el64, "ms_per_step": el64 / n64 * 1e3,
@@ -403,6 +444,7 @@ def main():
         H[0, :, 1] = (ke / (2 * math.pi)) * ph
         b = op.rhs(torch.from_numpy(E).to("cuda"), torch.from_numpy(H).to("cuda"))
         gm = {}
+        solutions = {}
 
         def solve(tag):
             torch.cuda.synchronize()
@@ -414,6 +456,7 @@ def main():
                  "precond_iters": info[0]["precond_iters"], "fallbacks": info[0]["fallbacks"]}
             log(f"GMRES {tag}: {r}")
             gm[tag] = r
+            solutions[tag] = ysol.cpu().numpy()[0]
 
         solve("mixed" if fp32 else "fp64")
         if fp32 and not args.no_fp64_gmres:
@@ -455,10 +498,49 @@ def main():
         res["batching"] = batching(log)
     if args.bodies32:
         res["bodies32"] = bodies32(log)
-    if not args.no_cpu:
-        ks = (2 * math.pi * math.sqrt(eps_i), 2 * math.pi * math.sqrt(eps_e))
-        w = np.full(surf.n, 4.0 * math.pi * args.radius ** 2 / surf.n) if args.ifgf_only else op.geometry(1)
-        res["cpu_baseline"] = cpu_baseline(surf, ks, w, args.cpu_rows)
+    if not args.no_cpu and not args.ifgf_only:
+        # the oracle (O1) on the nodes of args.oracle_patches patches, and the
+        # Mie error of the mixed GMRES solution, in the oracle's own program
+        mie_path = None
+        if gm and "mixed" in solutions:
+            import tempfile
+            mie_path = os.path.join(tempfile.mkdtemp(), "y.npy")
+            np.save(mie_path, solutions["mixed"])
+        o1 = oracle_sample(args, args.oracle_patches, log, mie_solution=mie_path)
+        rows = o1["rows"]
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+        err = {}
+        for form, g in gpu_forms.items():
+            sd = g["SD"][:, :, rows]
+            err["mixed" if form == "fp32" else form] = {
+                "S": max(rel(sd[q, :8], o1["SD"][q, :8]) for q in range(2)),
+                "D": max(rel(sd[q, 8:], o1["SD"][q, 8:]) for q in range(2)),
+                "Ay": rel(g["Ay"][:, rows], o1["Ay"])}
+        err["rows"] = f"{rows.size} points of {len(o1['patches'])} patches drawn from seed 2 " \
+                      f"({4 * rows.size} rows of A y); S, D: IFGF sums of densities from seed 3 vs " \
+                      f"direct sums; A y: unknowns from seed 2 vs the oracle's forward map"
+        err["within_tol"] = all(v[k] <= args.tol for v in err.values() if isinstance(v, dict) for k in v)
+        res["err_vs_o1"] = err
+        if "mie_rel_err" in o1:
+            res["mie_err"] = {"mixed_solution": float(o1["mie_rel_err"]),
+                              "points": f"1000 Fibonacci points at radius {0.7 * args.radius:g} (interior)"}
+        log(f"errors vs O1: {err}; Mie {res.get('mie_err')}")
+        t_rows = float(o1["seconds_forward"])
+        per_matvec = t_rows * surf.n / rows.size
+        o2s = o2_config1_seconds(st["Ps"], st["Pa"])
+        res["cpu_baseline"] = {
+            "value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": int(o1["nproc"]), "kind": "oracle",
+            "sample": f"oracle O1 forward map (direct regular sums, singular corrections, assembly) on "
+                      f"{rows.size} of {surf.n} points ({4 * rows.size} rows) took {t_rows:.1f} s over "
+                      f"{int(o1['nproc'])} worker processes (one BLAS thread each); extrapolated "
+                      f"x{surf.n / rows.size:.0f} to one matvec",
+            "cpu_model": cpu_model(), "nproc_host": os.cpu_count(),
+            "o2_config1_seconds": o2s,
+            "o2_note": f"reference IFGF (O2), one process, on the 1,536-point unit sphere at orders "
+                       f"({st['Ps']}, {st['Pa']}); at this workload's size it would take hours"}
     print(json.dumps(res), flush=True)
     op.close()
 

@@ -48,8 +48,12 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  * Ps, Pa: interpolation points per cone in the radial and in each angular
  *   variable (Sec. III-F; Remark 2 uses 3 and 5).  0 = chosen from `tol`.
  * ns_init, na_init: cone counts at level D+1 (Remark 2; Sec. IV uses 1, 2).
- * refine_radial: 0 doubles only the angular cone count per level when
- *   kappa*H_d > 1/2; 1 also doubles the radial count (literal Remark 2).
+ * refine_radial: 1 (default) doubles the radial and the angular cone counts
+ *   per level where kappa*H_d > 1/2 (Remark 2); 0 doubles only the angular
+ *   count, which is cheaper but whose radial interpolation error grows with
+ *   kappa*H of the coarse boxes (a radius-5 sphere at Ps, Pa = 5, 6: 8e-4 in
+ *   the single-layer and 2.5e-3 in the normal-derivative sums, against
+ *   1e-6 and 3e-5 with the radial doubling).
  * leaf_wavelengths: leaf boxes satisfy H_D <= leaf_wavelengths * lambda_min
  *   with lambda_min = 2 pi / max(k_int, k_ext) (Sec. III-G; 0.25).
  * precision: IFGF_FP64 or IFGF_FP32.
@@ -84,11 +88,12 @@ void ifgf_default_options(ifgf_options* opt);
  *  weights  host [n] FP64 quadrature weights (> 0), e.g. Fejer w_i w_j J_p
  *  k_int, k_ext  wavenumbers (> 0)
  *  tol      target relative accuracy in [1e-10, 1e-1]; selects Ps, Pa when
- *           the options leave them 0: tol >= 1e-3 -> (4, 5), >= 1e-4 ->
- *           (5, 6), >= 1e-5 -> (7, 8), else (8, 8), the smallest orders
- *           whose relative L2 error stayed below tol in every output block
- *           (S and the normal-derivative sums separately) on the test
- *           surfaces; below 1e-6 the largest orders do not reach tol
+ *           the options leave them 0: tol >= 1e-3 -> (3, 5) (the paper's),
+ *           >= 1e-4 -> (4, 6), >= 1e-5 -> (7, 8), else (8, 8), the smallest
+ *           orders whose relative L2 error (with refine_radial = 1) stayed
+ *           below tol in every output block (S and the normal-derivative
+ *           sums separately) on spheres of radius 1 to 5 wavelengths and an
+ *           ellipsoid; below 1e-6 the largest orders do not reach tol
  *  opt      NULL = defaults
  * Errors: IFGF_EINVAL (bad sizes, NaN/Inf, non-unit normals, weights <= 0,
  * k <= 0, tol out of range, duplicate points), IFGF_ENOMEM, IFGF_EHIP.     */

@@ -24,7 +24,9 @@ Follows Sec. III-E..III-I of the paper in its order and notation:
 Readings where the text is silent or garbled:
   A1  leaf size uses the shorter wavelength 2 pi / max(k0, k1);
   A2  a_d uses max(k0, k1); A3 the cone rule counts from level D+1 down;
-  A4  only the angular cone count doubles (refine_radial=True doubles n_s too);
+  A4  the radial and the angular cone counts both double (Remark 2 as written;
+      refine_radial=False doubles only the angular count, an alternative whose
+      radial interpolation error grows with kappa H on large boxes);
   A5  neighbours are the 27 boxes with ||j - k||_inf <= 1 (self included);
   A6  cone intervals half-open with the last closed: index = min(floor, n-1),
       phi = atan2(y, x) mapped to [0, 2 pi);
@@ -58,7 +60,7 @@ NS, ND = 8, 6
 
 class Params:
     def __init__(self, Ps=3, Pa=5, ns_init=1, na_init=2, leaf_wavelengths=0.25,
-                 refine_radial=False, kernel="helmholtz", deriv="analytic", fd_h=1e-6):
+                 refine_radial=True, kernel="helmholtz", deriv="analytic", fd_h=1e-6):
         self.Ps, self.Pa = Ps, Pa
         self.ns_init, self.na_init = ns_init, na_init
         self.leaf_wavelengths = leaf_wavelengths

@@ -121,14 +121,14 @@ const char* target_path(const ifgf_plan_s* p, int d) {
 }
 
 int tol_to_orders(double tol, int* Ps, int* Pa) {
-  // The smallest orders whose interpolation error stays below tol in every
-  // output block (the single-layer sums and, larger, their normal
-  // derivatives, whose angular part needs Pa > 5 below 2.5e-4), measured
-  // against direct sums on spheres and an ellipsoid at 4-6 points per
-  // interior wavelength.  The paper's (3, 5) (Remark 2) is reachable by
-  // setting the orders explicitly.
-  if (tol >= 1e-3) { *Ps = 4; *Pa = 5; }
-  else if (tol >= 1e-4) { *Ps = 5; *Pa = 6; }
+  // With the cone rule of Remark 2 (radial and angular counts doubled per
+  // level), the smallest orders whose interpolation error stays below tol in
+  // every output block: the single-layer sums and, larger, their normal
+  // derivatives, whose angular part needs Pa = 6 below 1.5e-4.  Measured
+  // against direct sums on spheres of radius 1 to 5 wavelengths and an
+  // ellipsoid.  tol >= 1e-3 gives the paper's (3, 5).
+  if (tol >= 1e-3) { *Ps = 3; *Pa = 5; }
+  else if (tol >= 1e-4) { *Ps = 4; *Pa = 6; }
   else if (tol >= 1e-5) { *Ps = 7; *Pa = 8; }
   else { *Ps = 8; *Pa = 8; }
   return 0;
@@ -203,7 +203,7 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->Pa = 0;
   opt->ns_init = 1;
   opt->na_init = 2;
-  opt->refine_radial = 0;
+  opt->refine_radial = 1;
   opt->leaf_wavelengths = 0.25;
   opt->precision = IFGF_FP64;
   opt->max_nrhs = 1;

@@ -36,7 +36,7 @@ def case_c1():
     return s, surf, nm_o
 
 
-@pytest.mark.parametrize("order", [(3, 5), (5, 5), (5, 6)])
+@pytest.mark.parametrize("order", [(3, 5), (4, 6)])
 def test_nmuller_apply_matches_oracle(case_c1, order):
     from paper_2408_02274_amd import NMullerOperator
     s, surf, nm_o = case_c1
