@@ -272,6 +272,97 @@ def learned_preconditioner(log, seed=5003):
     return out
 
 
+def waveguide(args, log):
+    """The large workload shaped like the paper's waveguide example (Sec. IV):
+    rounded rectangular box 40 x 1 x 0.5 wavelengths with edge radius 0.1,
+    patches of about 0.087 wavelengths with 10 x 10 nodes (16,704 patches,
+    1,670,400 points), eps 12.1 inside and 2.1 outside (k_int = 21.86, k_ext =
+    9.105).  Timed: one evaluation of the IFGF sums (16 S + 12 n.grad S at both
+    wavenumbers, the T_IFGF part of the paper's forward map) in FP32 with
+    FP32-sized workspaces, tol 1e-4; the error against the oracle's direct sums
+    on 4,096 random nodes; device memory of the plan.  The N-Mueller corrections
+    of this surface (about 1.6e9 (target, node) pairs at 64 bytes in FP64) do
+    not fit one GPU beside the cone buffers and are not built here."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2408_02274_amd import IFGFPlan
+    from paper_2408_02274_amd import binding as B
+    surf = synth.rounded_box((20.0, 0.5, 0.25), 0.1, 0.087, 10)
+    ks = (2 * math.pi * math.sqrt(12.1), 2 * math.pi * math.sqrt(2.1))
+    area = 8 * (20 * 0.5 + 20 * 0.25 + 0.5 * 0.25)            # outer box; the rounding removes < 1%
+    wconst = area / surf.n
+    free0 = torch.cuda.mem_get_info()[0]
+    t0 = time.perf_counter()
+    plan = IFGFPlan(surf.x, surf.normal, np.full(surf.n, wconst), ks[0], ks[1], 1e-4,
+                    precision=B.IFGF_FP32, fp32_workspaces=1, verbose=1)
+    plan_s = time.perf_counter() - t0
+    free1 = torch.cuda.mem_get_info()[0]
+    log(f"waveguide plan: n = {surf.n}, {plan_s:.1f} s, {(free0 - free1) / 2**30:.1f} GiB on the device")
+    phi = torch.from_numpy(synth.complex_normal((1, 8, surf.n), 3)).to("cuda")
+    out = torch.empty((1, 2, 14, surf.n), dtype=torch.complex128, device="cuda")
+    for _ in range(args.warmup):
+        plan.apply(phi, out)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(phi, out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = plan.stats()
+    plan.set_timing(False)
+    g = out.cpu().numpy()[0]
+    npts = st["Ps"] * st["Pa"] * st["Pa"]
+    kern = kernel_table(st, args.steps, npts)
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    achieved = d["flop"] / (d["ms"] * 1e-3)
+    roof = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK["fp32_mfma"] / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK["fp32_mfma"], "traffic": None,
+            "avg_launch_ms": d["ms"] / d["launches"], "flop_per_launch": d["flop"] / d["launches"]}
+    res = {"metric": "IFGF sums evaluations/s (T_IFGF part of the N-Mueller forward map)",
+           "value": args.steps / el, "unit": "evaluations/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"rounded box 40 x 1 x 0.5 wavelengths, edge radius 0.1, {surf.P} patches x "
+                                  f"10 x 10 nodes ({surf.n} points), k_int = {ks[0]:.3f}, k_ext = {ks[1]:.3f}, "
+                                  f"IFGF tol 1e-4, FP32 cone grids and FP32-sized workspaces",
+                      "Ps": st["Ps"], "Pa": st["Pa"], "D": st["D"], "plan_seconds": round(plan_s, 1),
+                      "device_GiB": round((free0 - free1) / 2**30, 2), "plan_device_bytes": st["device_bytes"]},
+           "roofline": roof,
+           "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in kern.items()},
+           "paper_context": "Table I row 5 (1,572,864 points): T_IFGF 50.14 s on 128 EPYC 7763 cores"}
+    plan.close()
+    if not args.no_cpu:
+        import tempfile
+        import subprocess
+        nproc = min(16, os.cpu_count() or 1)
+        o = os.path.join(tempfile.mkdtemp(), "o1.npz")
+        cmd = [sys.executable, "-m", "oracle.sample", "--geometry", "rounded_box", "--nc", "10",
+               "--direct-rows", "4096", "--k-int", repr(ks[0]), "--k-ext", repr(ks[1]),
+               "--weight", repr(wconst), "--nproc", str(nproc), "--out", o]
+        subprocess.run(cmd, cwd=ROOT, check=True, timeout=1200)
+        o1 = dict(np.load(o))
+        rows = o1["rows"]
+        gs = g[:, :, rows]
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+        res["err_vs_o1"] = {"S": max(rel(gs[q, :8], o1["SD"][q, :8]) for q in range(2)),
+                            "D": max(rel(gs[q, 8:], o1["SD"][q, 8:]) for q in range(2)),
+                            "rows": "4096 random nodes (seed 2), densities from seed 3"}
+        t = float(o1["seconds_direct"])
+        res["cpu_baseline"] = {
+            "value": rows.size / (t * surf.n), "unit": "evaluations/s", "cores": nproc, "kind": "oracle",
+            "sample": f"oracle O1 direct sums (S and n.grad S, 8 densities x 2 wavenumbers) on {rows.size} of "
+                      f"{surf.n} nodes took {t:.1f} s over {nproc} worker processes; extrapolated "
+                      f"x{surf.n / rows.size:.0f} to one evaluation", "cpu_model": cpu_model()}
+        log(f"waveguide errors vs O1: {res['err_vs_o1']}")
+    return res
+
+
 def kernel_table(st, steps, npts):
     kern = {}
     for name, t in st.get("timing", {}).items():
@@ -305,6 +396,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solves")
     ap.add_argument("--ifgf-only", action="store_true",
                     help="time the raw IFGF sums only (no N-Mueller plan: seconds to set up)")
+    ap.add_argument("--waveguide", action="store_true",
+                    help="the 1.67M-point rounded-box waveguide workload instead (IFGF sums; ~6 minutes)")
     ap.add_argument("--bodies32", action="store_true",
                     help="also time the 32-ellipsoid batch (host plans take ~5 minutes)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -324,6 +417,10 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.waveguide:
+        print(json.dumps(waveguide(args, log)), flush=True)
+        return
 
     if args.copy_calib > 0:
         nb = args.copy_calib << 20

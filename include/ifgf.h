@@ -64,7 +64,13 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  * batch_columns: right-hand sides stacked into the columns of one pass of
  *   the matrix-core kernels (1, 2 or 4; FP64 at most 2; 0 -> 1).  The cone
  *   buffers grow by that factor; whether it pays depends on the workload
- *   (ifgf_autotune measures it).                                            */
+ *   (ifgf_autotune measures it).
+ * fp32_workspaces: 1 with precision IFGF_FP32 sizes the cone buffers, the
+ *   per-pair target buffer and the density copy for FP32 values (half the
+ *   device memory of the default, which keeps room for the FP64 form); such a
+ *   plan cannot be switched to IFGF_FP64 (ifgf_set_precision: IFGF_EINVAL).
+ * verbose: 1 prints one progress line per planning stage and level on
+ *   stderr (large surfaces take minutes to plan).                          */
 typedef struct {
   int Ps, Pa;
   int ns_init, na_init;
@@ -74,6 +80,8 @@ typedef struct {
   int max_nrhs;
   int host_only;
   int batch_columns;
+  int fp32_workspaces;
+  int verbose;
 } ifgf_options;
 
 void ifgf_default_options(ifgf_options* opt);

@@ -17,6 +17,10 @@ from `seed`:
     representation at 1000 Fibonacci points of radius 0.7 R against the Mie
     series (the paper's accuracy check, Sec. IV-B).
 
+With --direct-rows K it computes only the direct regular sums S and D on K
+random nodes (seed `seed`) of a sphere or of the rounded box of the paper's
+waveguide example (Sec. IV), with constant weights and given wavenumbers.
+
 Every worker rebuilds the surface from the generator arguments and handles
 whole patches (the assembly differentiates per patch), one BLAS thread each.
 Output: an .npz with rows, S/D [2, 14, rows], Ay [4, rows], timings.
@@ -33,7 +37,14 @@ import numpy as np
 _W = {}
 
 
-def _init(npf, nc, radius, eps_e, eps_i, y_seed, phi_seed):
+def _surface(geom):
+    import synth
+    if geom["kind"] == "sphere":
+        return synth.cube_sphere(geom["npf"], geom["nc"], geom["radius"])
+    return synth.rounded_box(geom["half"], geom["edge"], geom["side"], geom["nc"])
+
+
+def _init(geom, eps_e, eps_i, y_seed, phi_seed):
     os.environ["OMP_NUM_THREADS"] = "1"
     try:
         from threadpoolctl import threadpool_limits
@@ -42,7 +53,8 @@ def _init(npf, nc, radius, eps_e, eps_i, y_seed, phi_seed):
         pass
     import synth
     from . import surface
-    s = synth.cube_sphere(npf, nc, radius)
+    s = _surface(geom)
+    _W["geo"] = s
     _W["surf"] = surface.PatchSurface(s.P, s.nc, s.x, s.du, s.dv)
     _W["eps"] = (eps_e, eps_i)
     _W["y"] = synth.complex_normal((4, s.n), y_seed)
@@ -59,6 +71,15 @@ def _forward_rows(chunk):
     return nm.rows, ay, sd, time.perf_counter() - t0
 
 
+def _direct_rows(args):
+    from . import direct
+    rows, w, ks = args
+    s = _W["geo"]
+    t0 = time.perf_counter()
+    sd = direct.regular_sums(s.x, s.normal, np.full(s.n, w), _W["phi"], ks, targets=rows, block=16)
+    return sd, time.perf_counter() - t0
+
+
 def _field_points(args):
     from . import nmuller
     y, pts = args
@@ -70,9 +91,17 @@ def _field_points(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--npf", type=int, required=True)
+    ap.add_argument("--geometry", default="sphere", choices=["sphere", "rounded_box"])
+    ap.add_argument("--npf", type=int, default=0)
     ap.add_argument("--nc", type=int, required=True)
-    ap.add_argument("--radius", type=float, required=True)
+    ap.add_argument("--radius", type=float, default=1.0)
+    ap.add_argument("--half", default="20,0.5,0.25", help="rounded box: outer half extents")
+    ap.add_argument("--edge", type=float, default=0.1, help="rounded box: edge radius")
+    ap.add_argument("--side", type=float, default=0.087, help="rounded box: patch side")
+    ap.add_argument("--direct-rows", type=int, default=0, help="direct sums only, on this many random nodes")
+    ap.add_argument("--weight", type=float, default=1.0, help="constant weight of the --direct-rows sums")
+    ap.add_argument("--k-int", type=float, default=0.0)
+    ap.add_argument("--k-ext", type=float, default=0.0)
     ap.add_argument("--eps-e", type=float, default=1.0)
     ap.add_argument("--eps-i", type=float, default=2.25)
     ap.add_argument("--npatch", type=int, default=11, help="patches sampled (0: Mie check only)")
@@ -84,13 +113,27 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     from multiprocessing import get_context
-    P = 6 * a.npf * a.npf
-    patches = np.sort(np.random.default_rng(a.seed).choice(P, a.npatch, replace=False))
-    res = {"patches": patches}
+    geom = ({"kind": "sphere", "npf": a.npf, "nc": a.nc, "radius": a.radius} if a.geometry == "sphere" else
+            {"kind": "rounded_box", "half": tuple(float(v) for v in a.half.split(",")), "edge": a.edge,
+             "side": a.side, "nc": a.nc})
+    res = {}
     ctx = get_context("spawn")
     with ctx.Pool(a.nproc, initializer=_init,
-                  initargs=(a.npf, a.nc, a.radius, a.eps_e, a.eps_i, a.y_seed, a.phi_seed)) as pool:
-        if a.npatch > 0:
+                  initargs=(geom, a.eps_e, a.eps_i, a.y_seed, a.phi_seed)) as pool:
+        if a.direct_rows > 0:
+            n = _surface(geom).n
+            rows = np.sort(np.random.default_rng(a.seed).choice(n, a.direct_rows, replace=False))
+            ks = (a.k_int, a.k_ext)
+            t0 = time.perf_counter()
+            parts = pool.map(_direct_rows, [(c, a.weight, ks) for c in np.array_split(rows, 4 * a.nproc)])
+            res["seconds_direct"] = time.perf_counter() - t0
+            res["rows"] = rows
+            res["SD"] = np.concatenate([p[0] for p in parts], axis=2)
+            res["n"] = n
+        elif a.npatch > 0:
+            P = 6 * a.npf * a.npf
+            patches = np.sort(np.random.default_rng(a.seed).choice(P, a.npatch, replace=False))
+            res["patches"] = patches
             t0 = time.perf_counter()
             parts = pool.map(_forward_rows, [[int(p)] for p in patches])
             res["seconds_forward"] = time.perf_counter() - t0

@@ -98,6 +98,7 @@ struct ifgf_plan_s {
   std::vector<TargetTiles> ttiles;      // ttiles[d]: target pairs by cone (matrix-core interpolation)
   void* d_res = nullptr;                // per-pair target contributions [pairs][28] complex
   unsigned* d_err = nullptr;            // device error word (bit 0: a propagation lock wait gave up)
+  int elem = 8;                         // bytes per real of the cone buffers and density copy
   int spin_limit = 1 << 22;             // attempts of the bounded lock wait
 };
 
@@ -209,6 +210,8 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->max_nrhs = 1;
   opt->host_only = 0;
   opt->batch_columns = 1;
+  opt->fp32_workspaces = 0;
+  opt->verbose = 0;
 }
 
 int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* normals,
@@ -245,6 +248,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   pp.na_init = opt.na_init;
   pp.refine_radial = opt.refine_radial;
   pp.leaf_wavelengths = opt.leaf_wavelengths;
+  pp.verbose = opt.verbose;
   std::string err;
   try {
     if (build_host_plan(p->host, n, points, normals, weights, k_int, k_ext, pp, err)) {
@@ -387,23 +391,25 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     return set_hip_error(e, "hipMemset");
   }
   // A matrix-core plan can run in either precision (ifgf_set_precision), so
-  // its FP32 density copy and FP64-sized cone buffers always exist.
+  // its density copy and cone buffers are sized for FP64 -- unless it was
+  // built FP32-only (fp32_workspaces), which halves them.
+  p->elem = (p->fp32 && opt.fp32_workspaces) ? 4 : 8;
   if (p->mfma) {
-    p->d_af = ar.alloc(sizeof(double) * 16 * (size_t)n * p->rcap);
+    p->d_af = ar.alloc((size_t)p->elem * 16 * (size_t)n * p->rcap);
     if (!p->d_af) {
       delete p;
       return set_error(IFGF_ENOMEM, "device workspace allocation failed");
     }
   }
   if (max_pairs > 0) {
-    p->d_res = ar.alloc(sizeof(double) * 56 * (size_t)max_pairs);
+    p->d_res = ar.alloc((size_t)p->elem * 56 * (size_t)max_pairs);
     if (!p->d_res) {
       delete p;
       return set_error(IFGF_ENOMEM, "device workspace allocation failed");
     }
   }
   if (p->max_slots > 0) {
-    size_t vb = p->mfma ? sizeof(double) * (size_t)p->max_slots * kslot_rows(opt.Ps, opt.Pa) * 32 * p->rcap
+    size_t vb = p->mfma ? (size_t)p->elem * (size_t)p->max_slots * kslot_rows(opt.Ps, opt.Pa) * 32 * p->rcap
                         : sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
     p->d_vals[0] = static_cast<double2*>(ar.alloc(vb));
     p->d_vals[1] = static_cast<double2*>(ar.alloc(vb));
@@ -593,7 +599,8 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
                   ",\"Ps\":" + std::to_string(H.Ps) + ",\"Pa\":" + std::to_string(H.Pa) +
                   ",\"near_pairs\":" + std::to_string(H.near_pairs) +
                   ",\"leaf_pairs\":" + std::to_string(H.leaf_pairs) +
-                  ",\"device_bytes\":" + std::to_string(p->arena.bytes()) + ",\"levels\":[";
+                  ",\"device_bytes\":" + std::to_string(p->arena.bytes()) +
+                  ",\"workspace_elem_bytes\":" + std::to_string(p->elem) + ",\"levels\":[";
   for (int d = 3; d <= H.D; ++d) {
     const HostLevel& L = H.lev[d];
     s += std::string(d > 3 ? "," : "") + "{\"d\":" + std::to_string(d) + ",\"boxes\":" +
@@ -681,6 +688,8 @@ int ifgf_set_precision(ifgf_plan_t p, int precision, int* previous) {
   if (p->opt.host_only) return set_error(IFGF_ENOTPLANNED, "plan was built with host_only");
   if (precision == IFGF_FP32 && !p->mfma)
     return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 or 6 and 3 <= Ps <= 6");
+  if (precision == IFGF_FP64 && p->elem < 8)
+    return set_error(IFGF_EINVAL, "the plan was built with fp32_workspaces: its buffers hold FP32 cone data only");
   if (previous) *previous = p->fp32 ? IFGF_FP32 : IFGF_FP64;
   p->fp32 = precision == IFGF_FP32;
   p->opt.precision = precision;

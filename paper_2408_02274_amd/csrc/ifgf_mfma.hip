@@ -410,12 +410,12 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       const int b = gl;
       if (b < nb) {
         const int4 rr = mine;
-        const int cnt = rr.w & 31;
+        const int cnt = rr.y & 31;
         const bool valid = r16 < cnt;
         const int p = valid ? (int)G.pts[rr.z + r16] : 0;
         pme = p;
-        const int cone = rr.w >> 5;
-        const double* cc = C.centers + 3 * (int64_t)rr.y;
+        const int cone = rr.w;
+        const double* cc = C.centers + 3 * (int64_t)(rr.y >> 5);
         const T dx = (T)(cc[0] - cp[0]), dy = (T)(cc[1] - cp[1]), dz = (T)(cc[2] - cp[2]);
         const T Yx = geo[p][0], Yy = geo[p][1], Yz = geo[p][2], rp = geo[p][3];
         const T zx = Yx - dx, zy = Yy - dy, zz = Yz - dz;
@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
       if (b >= nb) break;
-      const int cnt = rb[b].w & 31;
+      const int cnt = rb[b].y & 31;
       const T* Vs = Vc + (int64_t)rb[b].x * K * W + 4 * lane;
       const T* me = gb[16 * b + r16];
       T Ls[PS], Lt[PA];

@@ -10,9 +10,9 @@
 namespace ifgf {
 
 // Propagation work list for one parent level: the tiles of parent cone slot
-// q are [toff[q], toff[q+1]); rec[t] = (child cone slot, child box, index of
-// the tile's first parent point in pts, child cone << 5 | points in the tile)
-// and pts holds the parent interpolation point numbers of the groups.
+// q are [toff[q], toff[q+1]); rec[t] = (child cone slot, child box << 5 |
+// points in the tile, index of the tile's first parent point in pts, child
+// cone) and pts holds the parent interpolation point numbers of the groups.
 struct PropGroups {
   const int64_t* toff = nullptr;
   const int4* rec = nullptr;

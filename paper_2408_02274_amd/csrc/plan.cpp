@@ -13,7 +13,9 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <numeric>
 
 namespace ifgf {
@@ -186,9 +188,9 @@ void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts) {
         Pl.pt_t0[t] = (uint8_t)t0;
         int32_t* r = &Pl.pt_rec[4 * t];
         r[0] = Pl.pg_slot[g];
-        r[1] = Pl.pg_cbox[g];
+        r[1] = (Pl.pg_cbox[g] << 5) | std::min(16, Pl.pg_count[g] - t0);
         r[2] = (int32_t)(Pl.pg_start[g] + t0);
-        r[3] = (L.slot_cone[Pl.pg_slot[g]] << 5) | std::min(16, Pl.pg_count[g] - t0);
+        r[3] = L.slot_cone[Pl.pg_slot[g]];
       }
   }
   (void)L;
@@ -372,6 +374,13 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
   cheb_nodes(P.Ps, xs_);
   cheb_nodes(P.Pa, xa_);
 
+  const auto t_start = std::chrono::steady_clock::now();
+  auto progress = [&](const char* what, int d, int64_t count) {
+    if (!pp.verbose) return;
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    std::fprintf(stderr, "[ifgf plan] %7.1f s  %s level %d: %lld\n", s, what, d, (long long)count);
+    std::fflush(stderr);
+  };
   // relevant cones, top-down from level 3 (eq. rele_cone)
   for (int d = 3; d <= D; ++d) {
     HostLevel& L = P.lev[d];
@@ -439,6 +448,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
     }
     if (bad) { err = "internal: cousin target outside relevant cones"; return -1; }
     build_target_tiles(L, n);
+    progress("relevant cones and target pairs", d, L.nslots);
     // propagation pairs into level d-1
     if (d >= 4) {
       HostLevel& Pl = P.lev[d - 1];
@@ -473,7 +483,12 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
           err = "too many propagation pairs on one level for the 32-bit tile records";
           return -1;
         }
+        if (L.nb >= ((int64_t)1 << 26)) {
+          err = "too many boxes on one level for the tile records (child box << 5 | count)";
+          return -1;
+        }
         build_prop_groups(Pl, L, npts);
+        progress("propagation groups into", d - 1, Pl.pp_off[Pl.nslots]);
       }
     }
   }

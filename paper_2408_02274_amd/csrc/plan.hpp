@@ -51,8 +51,9 @@ struct HostLevel {
   std::vector<int32_t> pt_g;
   std::vector<uint8_t> pt_t0;
   // one record per tile, everything the propagation needs to start it:
-  // [tile][4] = child cone slot, child box, index of the tile's first point
-  // in pg_pts, child cone index << 5 | number of points (<= 16)
+  // [tile][4] = child cone slot, child box << 5 | number of points (<= 16),
+  // index of the tile's first point in pg_pts, child cone index (a cone index
+  // needs up to 31 bits: 2^30 cones per box at level 3 of a 40-wavelength body)
   std::vector<int32_t> pt_rec;
   // the target pairs grouped by cone slot (targets ascending within a slot),
   // cut into tiles of at most 8 targets: tile t covers entries
@@ -80,8 +81,9 @@ struct HostPlan {
 };
 
 struct PlanParams {
-  int Ps = 3, Pa = 5, ns_init = 1, na_init = 2, refine_radial = 0;
+  int Ps = 3, Pa = 5, ns_init = 1, na_init = 2, refine_radial = 1;
   double leaf_wavelengths = 0.25;
+  int verbose = 0;   // progress lines on stderr
 };
 
 // Returns 0 on success, else fills err.
