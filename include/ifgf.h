@@ -170,6 +170,11 @@ int ifgf_check(ifgf_plan_t plan, void* stream, unsigned* flags);
  * IFGF_EDEVICE while every kernel still runs to its end.                   */
 int ifgf_set_lock_spin_limit(ifgf_plan_t plan, int limit);
 
+/* Replace the normals of a built plan (host [n][3] FP64 unit vectors, caller
+ * order): the direction of the derivative sums at each point.  Synchronous.
+ * Errors: IFGF_EINVAL (null, non-unit), IFGF_EHIP.                          */
+int ifgf_set_normals(ifgf_plan_t plan, const double* normals);
+
 /* Switch per-kernel timing on (1) or off (0); either resets the totals.    */
 int ifgf_set_timing(ifgf_plan_t plan, int on);
 
@@ -177,6 +182,36 @@ void ifgf_destroy(ifgf_plan_t plan);
 
 /* Thread-local message of the last failed call ("" if none).               */
 const char* ifgf_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Sums at points other than the sources (off-surface field evaluation through
+ * the same IFGF; the paper's near-field maps, Sec. IV):
+ *   out[r][q][c][t]   = sum_m w_m phi_{r,c}(y_m) G_q(x_t, y_m),          c < 8
+ *   out[r][q][8+c][t] = sum_m w_m phi_{r,c}(y_m) d_t . grad G_q(x_t, y_m), c < 6
+ * at targets x_t with unit directions d_t; no term is excluded (targets must
+ * differ from every source).  One octree holds sources and targets; targets
+ * carry zero density.  Targets closer to the sources than a leaf box get the
+ * plain near sum, which is accurate only a few node spacings away from a
+ * discretised surface.
+ * ------------------------------------------------------------------------- */
+typedef struct ifgf_eval_s* ifgf_eval_t;
+
+/*  src, weights  host [n_src][3], [n_src] FP64 source points and weights
+ *  tgt, dirs     host [n_tgt][3] FP64 targets and unit directions
+ *  k_int, k_ext, tol, opt  as for ifgf_plan (host_only not supported)
+ * Errors: IFGF_EINVAL (also a target equal to a source), IFGF_ENOMEM,
+ * IFGF_EHIP.                                                                */
+int ifgf_eval_plan(ifgf_eval_t* out, int64_t n_src, const double* src, const double* weights,
+                   int64_t n_tgt, const double* tgt, const double* dirs, double k_int, double k_ext,
+                   double tol, const ifgf_options* opt);
+/*  densities device [nrhs][8][n_src] complex FP64; out device [nrhs][2][14][n_tgt]. */
+int ifgf_eval_apply(ifgf_eval_t ev, const void* densities, int nrhs, void* out, void* stream);
+/*  New target directions (host [n_tgt][3]); e.g. the three axes in turn give
+ *  the full gradient of the single-layer sums.  Synchronous.               */
+int ifgf_eval_set_directions(ifgf_eval_t ev, const double* dirs);
+/*  The IFGF plan over sources and targets (owned by ev; for statistics).    */
+ifgf_plan_t ifgf_eval_ifgf(ifgf_eval_t ev);
+void ifgf_eval_destroy(ifgf_eval_t ev);
 
 /* ---------------------------------------------------------------------------
  * N-Mueller operator (Sec. II eq. n_muller, k_delta, r_delta, t_delta) on a
@@ -225,6 +260,23 @@ int nmuller_apply(nmuller_t nm, const void* y, int nrhs, void* Ay, void* stream)
  * (t1, t2).  E, H device [nrhs][n][3] complex FP64 (incident fields at the
  * nodes); b device [nrhs][4][n].                                           */
 int nmuller_rhs(nmuller_t nm, const void* E, const void* H, int nrhs, void* b, void* stream);
+
+/* Incident field of an electric dipole at a complex source point (the
+ * end-face excitation of the paper's waveguide example, Sec. IV): moment p at
+ * x_s = x_0 + i b d radiates, for k b >> 1, a Gaussian beam of waist
+ * sqrt(2 b / k) along +d.  With R = x - x_s, r = sqrt(R.R) (principal branch),
+ * G = exp(i k r) / (4 pi r):
+ *   E = (k^2 G p + grad (p . grad G)) / eps,   H = -i omega grad G x p,
+ * an exact solution of curl E = i omega mu H, curl H = -i omega eps E away
+ * from the branch-cut disk {|x - x_0| <= b, (x - x_0) . d = 0} (b = 0: the
+ * ordinary point dipole).
+ *  points  device [n][3] FP64 evaluation points (n >= 0)
+ *  k, eps, omega  wavenumber, permittivity and frequency of the medium
+ *  dipole  host [12] FP64: p as 3 (re, im) pairs, x_0 [3], b d [3]
+ *  E, H    device [n][3] complex FP64, overwritten
+ * Errors: IFGF_EINVAL (null, non-finite or non-positive arguments).        */
+int ifgf_dipole_field(int64_t n, const void* points, double k, double eps, double omega,
+                      const double* dipole, void* E, void* H, void* stream);
 
 /* Host copies of surface quantities: which = 0 normals [n][3], 1 weights [n],
  * 2 t1 [n][3], 3 t2 [n][3], 4 Jacobians [n].                                */

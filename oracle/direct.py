@@ -49,3 +49,23 @@ def regular_sums(x, normals, weights, phi, kappas, targets=None, block=256):
             gd = g * (1j * k - 1.0 / r) / r * nd
             out[q, NS:, b0:b0 + t.size] = (gd @ a[:ND].T).T
     return out
+
+
+def sums_at(x, weights, phi, kappas, X, dirs, block=256):
+    """Direct sums at points X [M, 3] that are not sources (no term excluded):
+    out[q, c, t] = sum_m w_m phi_c(x_m) G_q(X_t, x_m) (c < 8) and
+    out[q, 8 + c, t] = sum_m w_m phi_c(x_m) dirs_t . grad_X G_q(X_t, x_m) (c < 6)."""
+    x = np.asarray(x, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    a = np.asarray(phi) * np.asarray(weights)[None, :]
+    out = np.zeros((2, NS + ND, X.shape[0]), dtype=np.complex128)
+    for b0 in range(0, X.shape[0], block):
+        d = X[b0:b0 + block, None, :] - x[None, :, :]
+        r = np.sqrt(np.sum(d * d, axis=2))
+        nd = np.sum(dirs[b0:b0 + block, None, :] * d, axis=2)
+        for q, k in enumerate(kappas):
+            g = np.exp(1j * k * r) / (4.0 * np.pi * r)
+            out[q, :NS, b0:b0 + block] = (g @ a.T).T
+            gd = g * (1j * k - 1.0 / r) / r * nd
+            out[q, NS:, b0:b0 + block] = (gd @ a[:ND].T).T
+    return out

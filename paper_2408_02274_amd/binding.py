@@ -73,6 +73,20 @@ def lib():
         L.ifgf_set_precision.argtypes = [vp, ci, C.POINTER(ci)]
         L.ifgf_autotune.argtypes = [vp, vp, C.POINTER(ci)]
         L.ifgf_check.argtypes = [vp, vp, C.POINTER(C.c_uint)]
+        L.ifgf_dipole_field.argtypes = [i64, vp, dbl, dbl, dbl, vp, vp, vp, vp]
+        L.ifgf_dipole_field.restype = ci
+        L.ifgf_set_normals.argtypes = [vp, vp]
+        L.ifgf_set_normals.restype = ci
+        L.ifgf_eval_plan.argtypes = [C.POINTER(vp), i64, vp, vp, i64, vp, vp, dbl, dbl, dbl, C.POINTER(Options)]
+        L.ifgf_eval_plan.restype = ci
+        L.ifgf_eval_apply.argtypes = [vp, vp, ci, vp, vp]
+        L.ifgf_eval_apply.restype = ci
+        L.ifgf_eval_set_directions.argtypes = [vp, vp]
+        L.ifgf_eval_set_directions.restype = ci
+        L.ifgf_eval_ifgf.argtypes = [vp]
+        L.ifgf_eval_ifgf.restype = vp
+        L.ifgf_eval_destroy.argtypes = [vp]
+        L.ifgf_eval_destroy.restype = None
         L.ifgf_set_lock_spin_limit.argtypes = [vp, ci]
         L.ifgf_autotune.restype = ci
         L.ifgf_set_precision.restype = ci
@@ -242,9 +256,76 @@ def ifgf_set_lock_spin_limit(plan, limit):
     _check(lib().ifgf_set_lock_spin_limit(plan, int(limit)), "ifgf_set_lock_spin_limit")
 
 
+def ifgf_dipole_field(points, k, eps, omega, p, x0, beam, stream=None):
+    """E, H [n][3] complex128 device tensors of a dipole p (3 complex) at the
+    complex source point x0 + i beam; points: device [n][3] float64."""
+    import torch
+    n = points.shape[0]
+    if points.dtype != torch.float64 or not points.is_contiguous() or tuple(points.shape[1:]) != (3,):
+        raise ValueError("points must be a contiguous float64 device tensor [n, 3]")
+    p = np.asarray(p, dtype=np.complex128)
+    dip = np.concatenate([np.stack([p.real, p.imag], axis=1).ravel(), np.asarray(x0, float),
+                          np.asarray(beam, float)]).astype(np.float64)
+    E = torch.empty((n, 3), dtype=torch.complex128, device=points.device)
+    H = torch.empty_like(E)
+    _check(lib().ifgf_dipole_field(int(n), points.data_ptr(), float(k), float(eps), float(omega),
+                                   dip.ctypes.data, E.data_ptr(), H.data_ptr(), _stream_ptr(stream)),
+           "ifgf_dipole_field")
+    return E, H
+
+
 def ifgf_destroy(plan):
     if plan:
         lib().ifgf_destroy(plan)
+
+
+class IFGFEval:
+    """Sums at target points other than the sources (ifgf_eval_*)."""
+
+    def __init__(self, src, weights, tgt, dirs, k_int, k_ext, tol=1e-4, **opts):
+        ns = int(np.asarray(src).shape[0])
+        self.nt = int(np.asarray(tgt).shape[0])
+        self.ns = ns
+        self.max_nrhs = int(opts.get("max_nrhs", 1))
+        x = _host_f64(src, (ns, 3))
+        w = _host_f64(weights, (ns,))
+        t = _host_f64(tgt, (self.nt, 3))
+        d = _host_f64(dirs, (self.nt, 3))
+        o = default_options()
+        for k, v in opts.items():
+            setattr(o, k, v)
+        h = C.c_void_p()
+        _check(lib().ifgf_eval_plan(C.byref(h), ns, x.ctypes.data, w.ctypes.data, self.nt, t.ctypes.data,
+                                    d.ctypes.data, float(k_int), float(k_ext), float(tol), C.byref(o)),
+               "ifgf_eval_plan")
+        self.handle = h.value
+
+    def set_directions(self, dirs):
+        d = _host_f64(dirs, (self.nt, 3))
+        _check(lib().ifgf_eval_set_directions(self.handle, d.ctypes.data), "ifgf_eval_set_directions")
+
+    def apply(self, densities, out=None, stream=None):
+        import torch
+        nrhs = densities.shape[0]
+        if densities.dtype != torch.complex128 or not densities.is_contiguous() or \
+                tuple(densities.shape[1:]) != (8, self.ns):
+            raise ValueError(f"densities must be a contiguous complex128 tensor [nrhs, 8, {self.ns}]")
+        if out is None:
+            out = torch.empty((nrhs, 2, 14, self.nt), dtype=torch.complex128, device=densities.device)
+        _check(lib().ifgf_eval_apply(self.handle, densities.data_ptr(), int(nrhs), out.data_ptr(),
+                                     _stream_ptr(stream)), "ifgf_eval_apply")
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().ifgf_eval_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class IFGFPlan:

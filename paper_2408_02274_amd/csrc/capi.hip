@@ -713,6 +713,26 @@ int ifgf_check(ifgf_plan_t p, void* stream, unsigned* flags) {
                                  "the sums of the applies since the last check are incomplete");
 }
 
+int ifgf_set_normals(ifgf_plan_t p, const double* normals) {
+  clear_error();
+  if (!p || !normals) return set_error(IFGF_EINVAL, "null argument");
+  HostPlan& H = p->host;
+  std::vector<double> s(3 * (size_t)H.n);
+  for (int64_t i = 0; i < H.n; ++i) {
+    const int64_t j = H.perm[i];
+    const double a = normals[3 * j], b = normals[3 * j + 1], c = normals[3 * j + 2];
+    if (!(std::fabs(std::sqrt(a * a + b * b + c * c) - 1.0) <= 1e-6))
+      return set_error(IFGF_EINVAL, "normal is not unit length at index " + std::to_string(j));
+    s[3 * i] = a;
+    s[3 * i + 1] = b;
+    s[3 * i + 2] = c;
+  }
+  H.nrm = s;
+  if (p->opt.host_only || !p->d_nrm) return IFGF_OK;
+  hipError_t e = hipMemcpy(p->d_nrm, s.data(), sizeof(double) * s.size(), hipMemcpyHostToDevice);
+  return e == hipSuccess ? IFGF_OK : set_hip_error(e, "hipMemcpy");
+}
+
 int ifgf_set_lock_spin_limit(ifgf_plan_t p, int limit) {
   clear_error();
   if (!p) return set_error(IFGF_EINVAL, "plan is NULL");

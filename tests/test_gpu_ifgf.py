@@ -260,3 +260,26 @@ def test_lock_wait_give_up_is_reported():
     p32.close()
     assert _rel(good, ref) < 1e-4
     assert _rel(bad, ref) > 1e-3                  # the skipped tiles are missing
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_long_body_with_deep_tree(prec):
+    """The waveguide's rounded box (40 x 1 x 0.5 wavelengths, eps 12.1 / 2.1)
+    on a coarse node grid (11,360 points): eleven levels, up to 512 x 1024 x
+    2048 cones per box at level 3 (cone indices near 2^30), against the direct
+    sums on every node, per block within 1e-4 at tol 1e-4."""
+    from paper_2408_02274_amd import IFGFPlan
+    s = synth.rounded_box((20.0, 0.5, 0.25), 0.1, 0.6, 4)
+    ks = (2 * math.pi * math.sqrt(12.1), 2 * math.pi * math.sqrt(2.1))
+    w = np.random.default_rng(33).uniform(0.5, 1.5, s.n) * 1e-3
+    phi = synth.complex_normal((1, 8, s.n), 34)
+    _say(f"[gpu] ifgf long body n={s.n} precision={prec}")
+    plan = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-4, precision=prec, fp32_workspaces=prec)
+    c = plan.counts()
+    assert c[1] == 11 and c[7 + 3] >> 16 == 512          # D, and n_s at level 3
+    g = plan.apply(torch.from_numpy(phi).to("cuda")).cpu().numpy()[0]
+    plan.close()
+    o1 = direct.regular_sums(s.x, s.normal, w, phi[0], ks)
+    errs = [_rel(g[q, :8], o1[q, :8]) for q in range(2)] + [_rel(g[q, 8:], o1[q, 8:]) for q in range(2)]
+    _say(f"    vs direct sum: S {errs[:2]}, D {errs[2:]}")
+    assert max(errs) < 1e-4

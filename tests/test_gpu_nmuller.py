@@ -91,3 +91,28 @@ def test_homogeneous_medium_is_identity():
     op.close()
     want = np.stack([1.5 * y[0, 0], 1.5 * y[0, 1], 2.0 * y[0, 2], 2.0 * y[0, 3]])
     assert np.allclose(g, want, rtol=0, atol=1e-12)
+
+
+def test_dipole_excitation_matches_oracle():
+    """Complex-source-point dipole (waveguide end-face excitation): device
+    fields at the nodes of the rounded box, and of the ordinary dipole at
+    random points, equal the oracle's to 1e-12."""
+    from paper_2408_02274_amd import binding as B
+    from oracle import excitation
+    s = synth.rounded_box((20.0, 0.5, 0.25), 0.1, 0.6, 4)
+    ke = 2 * math.pi * math.sqrt(2.1)
+    b = ke * 0.4 ** 2 / 2
+    x0, beam, p = np.array([-20.5, 0.0, 0.0]), np.array([b, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    _say("[gpu] dipole field at complex source point")
+    pts = torch.from_numpy(np.ascontiguousarray(s.x)).to("cuda")
+    E, H = B.ifgf_dipole_field(pts, ke, 2.1, 2 * math.pi, p, x0, beam)
+    Eo, Ho = excitation.dipole_fields(s.x, ke, 2.1, 2 * math.pi, p, x0, beam)
+    assert np.linalg.norm(E.cpu().numpy() - Eo) < 1e-12 * np.linalg.norm(Eo)
+    assert np.linalg.norm(H.cpu().numpy() - Ho) < 1e-12 * np.linalg.norm(Ho)
+    # b = 0: the ordinary dipole, at random points
+    X = np.random.default_rng(3).uniform(-2, 2, (500, 3))
+    E0, H0 = B.ifgf_dipole_field(torch.from_numpy(X).to("cuda"), ke, 2.1, 2 * math.pi, p + 0.5j, np.zeros(3) + 5,
+                                 np.zeros(3))
+    Eo0, Ho0 = excitation.dipole_fields(X, ke, 2.1, 2 * math.pi, p + 0.5j, np.zeros(3) + 5, np.zeros(3))
+    assert np.linalg.norm(E0.cpu().numpy() - Eo0) < 1e-12 * np.linalg.norm(Eo0)
+    assert np.linalg.norm(H0.cpu().numpy() - Ho0) < 1e-12 * np.linalg.norm(Ho0)

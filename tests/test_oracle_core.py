@@ -91,3 +91,27 @@ def test_rounded_box_area_and_volume_closed_forms():
     assert np.max(np.abs((surf.w[:, None] * s.normal).sum(0))) < 1e-9 * area
     # outward normals agree with the patch orientation
     assert np.all(np.sum(surf.n * s.normal, axis=1) > 0.999)
+
+
+def test_sums_at_off_node_points_match_regular_sums():
+    # the sums at a point that is not a source equal the regular sums of the
+    # source set extended by that point, at that point (its own term excluded)
+    import math
+    import numpy as np
+    import synth
+    from oracle import direct
+    s = synth.cube_sphere(1, 5, 1.0)
+    rng = np.random.default_rng(7)
+    w = rng.uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((8, s.n), 8)
+    X = np.array([[0.2, -0.3, 0.4], [1.3, 0.1, -0.2]])
+    dirs = np.array([[0.0, 0.6, 0.8], [1.0, 0.0, 0.0]])
+    ks = (2.5 * math.pi, 1.5 * math.pi)
+    got = direct.sums_at(s.x, w, phi, ks, X, dirs)
+    for t in range(2):
+        x = np.vstack([s.x, X[t:t + 1]])
+        nrm = np.vstack([s.normal, dirs[t:t + 1]])
+        ww = np.r_[w, 1.0]
+        ph = np.hstack([phi, rng.standard_normal((8, 1))])
+        want = direct.regular_sums(x, nrm, ww, ph, ks, targets=[s.n])
+        assert np.allclose(got[:, :, t], want[:, :, 0], rtol=1e-13, atol=0)
