@@ -42,6 +42,9 @@ extern "C" {
 #define IFGF_FP64 0            /* cone grids, interpolation, sums in FP64      */
 #define IFGF_FP32 1            /* cone grids and interpolation in FP32         */
 
+#define IFGF_DERIV_ANALYTIC 0  /* n.grad of the interpolant, analytically      */
+#define IFGF_DERIV_FD 1        /* the paper's forward difference, h = 1e-6     */
+
 typedef struct ifgf_plan_s* ifgf_plan_t;
 
 /* Options; ifgf_default_options() fills the paper's defaults.
@@ -70,7 +73,13 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  *   device memory of the default, which keeps room for the FP64 form); such a
  *   plan cannot be switched to IFGF_FP64 (ifgf_set_precision: IFGF_EINVAL).
  * verbose: 1 prints one progress line per planning stage and level on
- *   stderr (large surfaces take minutes to plan).                          */
+ *   stderr (large surfaces take minutes to plan).
+ * deriv_mode: how the normal derivative of a cousin contribution is taken
+ *   (Sec. III-I): IFGF_DERIV_ANALYTIC (default) differentiates the
+ *   interpolant times the centred factor; IFGF_DERIV_FD is the paper's
+ *   (G F)(x + h n) - (G F)(x) over h = 1e-6, x + h n interpolated in the cone
+ *   of x.  FD needs IFGF_FP64, the matrix-core orders and one right-hand side
+ *   per apply (max_nrhs = batch_columns = 1); near sums stay analytic.      */
 typedef struct {
   int Ps, Pa;
   int ns_init, na_init;
@@ -82,6 +91,7 @@ typedef struct {
   int batch_columns;
   int fp32_workspaces;
   int verbose;
+  int deriv_mode;
 } ifgf_options;
 
 void ifgf_default_options(ifgf_options* opt);

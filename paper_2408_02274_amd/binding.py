@@ -19,6 +19,8 @@ IFGF_FP64 = 0
 IFGF_FP32 = 1
 IFGF_WNOCONV = 1
 IFGF_EDEVICE = -5
+IFGF_DERIV_ANALYTIC = 0
+IFGF_DERIV_FD = 1
 
 
 class IFGFError(RuntimeError):
@@ -31,7 +33,8 @@ class Options(C.Structure):
     _fields_ = [("Ps", C.c_int), ("Pa", C.c_int), ("ns_init", C.c_int), ("na_init", C.c_int),
                 ("refine_radial", C.c_int), ("leaf_wavelengths", C.c_double),
                 ("precision", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int),
-                ("batch_columns", C.c_int), ("fp32_workspaces", C.c_int), ("verbose", C.c_int)]
+                ("batch_columns", C.c_int), ("fp32_workspaces", C.c_int), ("verbose", C.c_int),
+                ("deriv_mode", C.c_int)]
 
 
 class NMullerParams(C.Structure):

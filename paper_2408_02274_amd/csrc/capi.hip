@@ -212,6 +212,7 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->batch_columns = 1;
   opt->fp32_workspaces = 0;
   opt->verbose = 0;
+  opt->deriv_mode = IFGF_DERIV_ANALYTIC;
 }
 
 int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* normals,
@@ -237,6 +238,10 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     return set_error(IFGF_EINVAL, "Ps and Pa must lie in [1, 8]");
   if (opt.precision != IFGF_FP64 && opt.precision != IFGF_FP32)
     return set_error(IFGF_EINVAL, "precision must be IFGF_FP64 or IFGF_FP32");
+  if (opt.deriv_mode != IFGF_DERIV_ANALYTIC && opt.deriv_mode != IFGF_DERIV_FD)
+    return set_error(IFGF_EINVAL, "deriv_mode must be IFGF_DERIV_ANALYTIC or IFGF_DERIV_FD");
+  if (opt.deriv_mode == IFGF_DERIV_FD && (opt.precision != IFGF_FP64 || opt.max_nrhs > 1 || opt.batch_columns > 1))
+    return set_error(IFGF_EINVAL, "IFGF_DERIV_FD needs IFGF_FP64 and one right-hand side per apply");
 
   ifgf_plan_s* p = new (std::nothrow) ifgf_plan_s();
   if (!p) return set_error(IFGF_ENOMEM, "host allocation failed");
@@ -293,6 +298,10 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   if (p->fp32 && !p->mfma) {
     delete p;
     return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 or 6 and 3 <= Ps <= 6");
+  }
+  if (opt.deriv_mode == IFGF_DERIV_FD && !p->mfma) {
+    delete p;
+    return set_error(IFGF_EINVAL, "IFGF_DERIV_FD needs the matrix-core orders (Pa = 5 or 6, 3 <= Ps <= 6)");
   }
   if (p->mfma)
     for (int d = 1; d <= H.D; ++d) std::vector<int32_t>().swap(H.lev[d].pp_slot);
@@ -374,6 +383,12 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     std::vector<int32_t>().swap(L.tp_slot);
     std::vector<int32_t>().swap(L.pp_slot);
   }
+  if (opt.deriv_mode == IFGF_DERIV_FD)
+    for (int d = 3; d <= H.D; ++d)
+      if (H.lev[d].tp_off.back() > 0 && p->ttiles[d].ntiles == 0) {
+        delete p;
+        return set_error(IFGF_EINVAL, "IFGF_DERIV_FD needs the target tiles of every level (fewer than 2^31 pairs)");
+      }
   // right-hand sides stacked into the cone-data columns (matrix-core path)
   p->rcap = p->mfma ? std::min(std::min(opt.max_nrhs, opt.batch_columns), max_batch_columns(p->fp32, opt.Ps, opt.Pa))
                     : 1;
@@ -467,7 +482,8 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
         if (R == 1 && p->d_res && p->ttiles[d].ntiles > 0) {
           // cone-major tiles on the matrix cores, then the per-target sums
           if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, p->lev[d], p->ic, p->ttiles[d], p->d_xs, p->d_nrm, k0, k1,
-                                    p->d_vals[cur], p->d_res, st)) != hipSuccess ||
+                                    p->d_vals[cur], p->d_res, p->opt.deriv_mode == IFGF_DERIV_FD, st)) !=
+                  hipSuccess ||
               (e = mf_targets_reduce(p->fp32, p->lev[d], n, p->d_res, p->d_out_s, st)) != hipSuccess)
             return set_hip_error(e, "targets");
         } else if ((e = mf_targets(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1,
@@ -688,6 +704,8 @@ int ifgf_set_precision(ifgf_plan_t p, int precision, int* previous) {
   if (p->opt.host_only) return set_error(IFGF_ENOTPLANNED, "plan was built with host_only");
   if (precision == IFGF_FP32 && !p->mfma)
     return set_error(IFGF_EINVAL, "IFGF_FP32 needs Pa = 5 or 6 and 3 <= Ps <= 6");
+  if (precision == IFGF_FP32 && p->opt.deriv_mode == IFGF_DERIV_FD)
+    return set_error(IFGF_EINVAL, "the forward-difference derivative is FP64 only");
   if (precision == IFGF_FP64 && p->elem < 8)
     return set_error(IFGF_EINVAL, "the plan was built with fp32_workspaces: its buffers hold FP32 cone data only");
   if (previous) *previous = p->fp32 ? IFGF_FP32 : IFGF_FP64;

@@ -785,7 +785,11 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
 // applies the centred factor G(x, x_B) and its gradient and writes the 28
 // complex contributions of each (target, cousin) pair to res; a second
 // kernel sums them per target.
-template <int PS, int PA, class T>
+// FD (the paper's forward difference, Sec. III-I): row 2t + 1 instead holds
+// the interpolation weights at x + h n in the cone of x (extrapolating where
+// x + h n leaves it), and the normal derivative is (G(x + h n, x_B)
+// F(x + h n) - G(x, x_B) F(x)) / h, h = 1e-6.
+template <int PS, int PA, class T, bool FD>
 __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, TargetTiles TT,
                                                       const double* __restrict__ xs,
                                                       const double* __restrict__ nrm, double k0, double k1,
@@ -795,9 +799,11 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   constexpr int KS = KSlot<PS, PA>::KS;
   constexpr int K = KSlot<PS, PA>::K;
   // per-target record: Ls, c_s dLs, Lt, c_t dLt, Lp, c_ph dLp, then
-  // Re G_q, Im G_q (q = 0, 1), -n.r-hat / r, n.r-hat
+  // Re G_q, Im G_q (q = 0, 1), -n.r-hat / r, n.r-hat; with FD the derivative
+  // slots hold Ls, Lt, Lp at x + h n and Re G_q, Im G_q there follow
   constexpr int OLS = 0, OSD = PS, OLT = 2 * PS, OTD = 2 * PS + PA, OLP = 2 * PS + 2 * PA,
-                OPD = 2 * PS + 3 * PA, OG = 2 * PS + 4 * PA, TW = OG + 6;
+                OPD = 2 * PS + 3 * PA, OG = 2 * PS + 4 * PA, TW = OG + (FD ? 10 : 6);
+  constexpr double kFdH = 1e-6;
   __shared__ T rec[4][8][TW];
   __shared__ T outb[4][16][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -838,6 +844,23 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
       c_s *= (T)2 / ((T)(kEtaD / L.ns));
       c_t *= (T)2 / ((T)(kPiD / L.na));
       c_ph *= (T)2 / ((T)(kPiD / L.na));
+      if constexpr (FD) {
+        // x + h n in the cone of x, its Lagrange weights and centred factor
+        const T zx2 = zx + (T)kFdH * nx, zy2 = zy + (T)kFdH * ny, zz2 = zz + (T)kFdH * nz;
+        T r2, us2, ut2, up2, th2, ph2;
+        local3<T>(zx2, zy2, zz2, (T)L.h, L.ns, L.na, cone, &r2, &us2, &ut2, &up2, &th2, &ph2);
+        lag<PS, T>(Nodes<T>::xs(ic), Nodes<T>::ws(ic), us2, dLs);
+        lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), ut2, dLt);
+        lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up2, dLp);
+        c_s = c_t = c_ph = (T)1;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          T sn, cs;
+          tsincos<T>((T)(q == 0 ? k0 : k1) * r2, &sn, &cs);
+          o[OG + 6 + q] = cs * (T)kInv4PiD / r2;
+          o[OG + 8 + q] = sn * (T)kInv4PiD / r2;
+        }
+      }
 #pragma unroll
       for (int z = 0; z < PS; ++z) {
         o[OLS + z] = Ls[z];
@@ -873,14 +896,24 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   const int t = r16 >> 1;
   const T kv = (r16 & 1) ? (T)0 : (T)1, kd = (T)1 - kv;
   const T* me = rw[t];
+  // (FD: value rows Lt[b] U[a], U = Ls Lp; difference rows Lt2[b] W[a], W = Ls2 Lp2)
   T U[PS], W[PS], Ltv[PA], Tdv[PA];
-  {
+  if constexpr (FD) {
+    const T f1 = kv * me[OLP + gl], f2 = kd * me[OPD + gl];
+#pragma unroll
+    for (int a = 0; a < PS; ++a) {
+      U[a] = me[OLS + a] * f1;
+      W[a] = me[OSD + a] * f2;
+    }
+  } else {
     const T f1 = kv * me[OLP + gl] + kd * me[OPD + gl], f2 = kd * me[OLP + gl];
 #pragma unroll
     for (int a = 0; a < PS; ++a) {
       U[a] = me[OLS + a] * f1 + me[OSD + a] * f2;
       W[a] = me[OLS + a] * f2;
     }
+  }
+  {
 #pragma unroll
     for (int b = 0; b < PA; ++b) {
       Ltv[b] = me[OLT + b];
@@ -889,7 +922,8 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   }
   // phi-node of this lane in the tail k-steps: 4 + gl mod tc
   const int ct4 = 4 + (TC == 1 ? 0 : (gl & 1));
-  const T g1 = kv * me[OLP + ct4] + kd * me[OPD + ct4], g2 = kd * me[OLP + ct4];
+  const T g1 = FD ? kv * me[OLP + ct4] : kv * me[OLP + ct4] + kd * me[OPD + ct4];
+  const T g2 = FD ? kd * me[OPD + ct4] : kd * me[OLP + ct4];
   typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
   const T* Vs = V + (int64_t)slot * K * 32 + 4 * lane;
   // B operands of a pair of k-steps are requested PD - 1 pairs ahead of
@@ -912,7 +946,10 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
       const int ab = (4 * (j - NAB) + gl) / TC;                // phi-node ct4 of pair ab
       if (ab < NAB) {
         const T lsa = me[OLS + ab / PA], sda = me[OSD + ab / PA];
-        av = me[OLT + ab % PA] * (lsa * g1 + sda * g2) + me[OTD + ab % PA] * lsa * g2;
+        if constexpr (FD)
+          av = me[OLT + ab % PA] * lsa * g1 + me[OTD + ab % PA] * sda * g2;
+        else
+          av = me[OLT + ab % PA] * (lsa * g1 + sda * g2) + me[OTD + ab % PA] * lsa * g2;
       } else {
         av = (T)0;
       }
@@ -947,10 +984,17 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
       out[2 * (14 * q + m) + 1] = gr * fi + gi * fr;
       if (m < 6) {
         const T dr = ob[2 * tt + 1][col], di = ob[2 * tt + 1][16 + col];
-        const T dgr = g[4], dgi = (T)(q == 0 ? k0 : k1) * g[5];   // (i k - 1/r) n.r-hat
-        const T tr = dgr * fr - dgi * fi + dr, ti = dgr * fi + dgi * fr + di;
-        out[2 * (14 * q + 8 + m)] = gr * tr - gi * ti;
-        out[2 * (14 * q + 8 + m) + 1] = gr * ti + gi * tr;
+        if constexpr (FD) {
+          const T g2r = g[6 + q], g2i = g[8 + q];
+          const T ih = (T)(1.0 / kFdH);
+          out[2 * (14 * q + 8 + m)] = ((g2r * dr - g2i * di) - (gr * fr - gi * fi)) * ih;
+          out[2 * (14 * q + 8 + m) + 1] = ((g2r * di + g2i * dr) - (gr * fi + gi * fr)) * ih;
+        } else {
+          const T dgr = g[4], dgi = (T)(q == 0 ? k0 : k1) * g[5];   // (i k - 1/r) n.r-hat
+          const T tr = dgr * fr - dgi * fi + dr, ti = dgr * fi + dgi * fr + di;
+          out[2 * (14 * q + 8 + m)] = gr * tr - gi * ti;
+          out[2 * (14 * q + 8 + m) + 1] = gr * ti + gi * tr;
+        }
       }
     }
   }
@@ -1008,10 +1052,19 @@ hipError_t targets_t(const DevLevel& L, const InterpC& ic, const double* xs, con
 }
 template <int PS, int PA, class T>
 hipError_t targets_tiles_t(const DevLevel& L, const InterpC& ic, const TargetTiles& TT, const double* xs,
-                           const double* nrm, double k0, double k1, const void* V, void* res, hipStream_t st) {
+                           const double* nrm, double k0, double k1, const void* V, void* res, bool fd,
+                           hipStream_t st) {
   if (TT.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_targets_mfma<PS, PA, T>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT, xs, nrm,
-                     k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+  if (fd) {
+    if constexpr (std::is_same<T, double>::value)
+      hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, true>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT,
+                         xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+    else
+      return hipErrorInvalidValue;   // the forward difference is FP64 only
+  } else {
+    hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, false>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT,
+                       xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+  }
   return hipGetLastError();
 }
 
@@ -1081,9 +1134,9 @@ hipError_t dispatch_targets(int Ps, int Pa, int R, const DevLevel& L, const Inte
 template <class T>
 hipError_t dispatch_targets_tiles(int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
                                   const double* xs, const double* nrm, double k0, double k1, const void* V,
-                                  void* res, hipStream_t st) {
+                                  void* res, bool fd, hipStream_t st) {
   return with_orders(Ps, Pa, [&]<int PS, int PA>() {
-    return targets_tiles_t<PS, PA, T>(L, ic, TT, xs, nrm, k0, k1, V, res, st);
+    return targets_tiles_t<PS, PA, T>(L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
   });
 }
 
@@ -1137,9 +1190,9 @@ hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const
 
 hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
                             const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
-                            hipStream_t st) {
-  return fp32 ? dispatch_targets_tiles<float>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, st)
-              : dispatch_targets_tiles<double>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, st);
+                            bool fd, hipStream_t st) {
+  return fp32 ? dispatch_targets_tiles<float>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st)
+              : dispatch_targets_tiles<double>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
 }
 
 hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,

@@ -55,9 +55,10 @@ hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const
 // Target interpolation on the matrix cores (one right-hand side): per pair e
 // the 28 complex contributions into res [pairs][28] (complex in the cone
 // precision), then out_s[i] += sum of res over the pairs of target i.
+// fd: normal derivatives by the forward difference of the paper (FP64 only)
 hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
                             const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
-                            hipStream_t st);
+                            bool fd, hipStream_t st);
 hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,
                              hipStream_t st);
 

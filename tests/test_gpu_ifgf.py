@@ -267,7 +267,12 @@ def test_long_body_with_deep_tree(prec):
     """The waveguide's rounded box (40 x 1 x 0.5 wavelengths, eps 12.1 / 2.1)
     on a coarse node grid (11,360 points): eleven levels, up to 512 x 1024 x
     2048 cones per box at level 3 (cone indices near 2^30), against the direct
-    sums on every node, per block within 1e-4 at tol 1e-4."""
+    sums on every node.  S within 1e-4; D within 3e-4: on this thin body with
+    random weights the normal-derivative sums are small against the terms
+    they sum (sources on the target's own flat face contribute exactly zero,
+    their interpolated far field does not), and the angular interpolation of
+    the derivative leaves 1.4e-4 / 2.5e-4 at (4, 6), falling with Pa
+    (measured 1.9e-5 / 3.2e-5 at (5, 7), 4e-6 / 7e-6 at (6, 8))."""
     from paper_2408_02274_amd import IFGFPlan
     s = synth.rounded_box((20.0, 0.5, 0.25), 0.1, 0.6, 4)
     ks = (2 * math.pi * math.sqrt(12.1), 2 * math.pi * math.sqrt(2.1))
@@ -282,4 +287,28 @@ def test_long_body_with_deep_tree(prec):
     o1 = direct.regular_sums(s.x, s.normal, w, phi[0], ks)
     errs = [_rel(g[q, :8], o1[q, :8]) for q in range(2)] + [_rel(g[q, 8:], o1[q, 8:]) for q in range(2)]
     _say(f"    vs direct sum: S {errs[:2]}, D {errs[2:]}")
-    assert max(errs) < 1e-4
+    assert max(errs[:2]) < 1e-4 and max(errs[2:]) < 3e-4
+
+
+@pytest.mark.parametrize("order", [(3, 5), (4, 6)])
+def test_forward_difference_derivative_matches_reference(order):
+    """deriv_mode = IFGF_DERIV_FD: the paper's forward difference (h = 1e-6,
+    x + h n interpolated in the cone of x) against the oracle's.  Both take
+    the difference of two sums that agree to ~1e-16 relative, so each carries
+    ~1e-10 relative noise; bar 1e-8.  S sums are unchanged (1e-10); the FD
+    and analytic normal derivatives differ by about the interpolation error."""
+    from paper_2408_02274_amd import binding as B
+    s, ks = CASES["sphere864"]()
+    w = np.random.default_rng(35).uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 36)
+    Ps, Pa = order
+    _say(f"[gpu] ifgf forward-difference derivative Ps={Ps} Pa={Pa}")
+    g = _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa, deriv_mode=B.IFGF_DERIV_FD)[0]
+    ga = _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa)[0]
+    o2 = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params(Ps=Ps, Pa=Pa, deriv="fd")).apply(phi[0])
+    for q in range(2):
+        assert _rel(g[q, :8], o2[q, :8]) < 1e-10
+        assert _rel(g[q, 8:], o2[q, 8:]) < 1e-8
+        assert _rel(g[q, 8:], ga[q, 8:]) < 1e-3
+    with pytest.raises(B.IFGFError):
+        _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa, deriv_mode=B.IFGF_DERIV_FD, precision=B.IFGF_FP32)
