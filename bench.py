@@ -268,6 +268,9 @@ def learned_preconditioner(log, seed=5003):
         out[k] = {"iters": r[k]["iters"], "seconds": r[k]["wall"], "true_relres": r[k]["true_relres"],
                   "converged": r[k]["converged"], "fallbacks": r[k]["fallbacks"]}
     out["learned_vs_plain_seconds"] = r["learned"]["wall"] / r["plain"]["wall"]
+    out["learned_vs_scaling_only_seconds"] = r["learned"]["wall"] / r["scaling_only"]["wall"]
+    out["note"] = ("the network is judged against M = D^-1 alone, its fixed part: a ratio above 1 means the "
+                   "learned correction costs time")
     log(f"learned preconditioner: {out}")
     return out
 

@@ -271,11 +271,12 @@ def test_fgmres_with_scaling_preconditioner_and_fallbacks():
     op.close()
 
 
-def test_trained_preconditioner_gain_on_held_out_body():
+@pytest.fixture(scope="module")
+def held_out_solves():
     """The committed network (trained on operator-generated pairs of the
-    ellipsoid family, seeds 6000+) on held-out body 5002: flexible GMRES with
-    it needs fewer iterations than plain GMRES to the same FP64 true
-    residual; M = D^-1 alone is reported beside it (it does better still)."""
+    ellipsoid family, seeds 6000+) on held-out body 5002: plain GMRES,
+    flexible GMRES with M = D^-1 alone, and with the network, each to a 1e-4
+    FP64 true residual."""
     import os
     from paper_2408_02274_amd import precond
     path = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_2408_02274_amd", "weights",
@@ -287,9 +288,22 @@ def test_trained_preconditioner_gain_on_held_out_body():
     op = precond.make_operator(surf, eps)
     b = precond.plane_wave_rhs(op, surf, 5002)
     r = precond.evaluate(op, b, params, dims, rtol=1e-4, maxit=800)
+    op.close()
     _say({k: (r[k]["iters"], round(r[k]["wall"], 2), r[k]["fallbacks"]) for k in ("plain", "scaling_only", "learned")})
+    return r
+
+
+def test_trained_preconditioner_converges_without_fallback(held_out_solves):
+    r = held_out_solves
     for k in ("plain", "scaling_only", "learned"):
         assert r[k]["converged"] and r[k]["true_relres"] <= 1e-4
     assert r["learned"]["fallbacks"] == 0
     assert r["learned"]["iters"] < r["plain"]["iters"]
-    op.close()
+
+
+@pytest.mark.xfail(strict=False, reason="the learned correction does not beat its fixed part M = D^-1: on "
+                                        "held-out body 5003 it took 229 iterations / 4.76 s against 199 / "
+                                        "4.14 s for D^-1 alone (plain GMRES 311 / 6.36 s)")
+def test_trained_preconditioner_beats_its_fixed_part(held_out_solves):
+    r = held_out_solves
+    assert r["learned"]["wall"] < r["scaling_only"]["wall"] < r["plain"]["wall"]
