@@ -163,10 +163,31 @@ def batching(log, reps=5):
     t_batch = clock(lambda: op.apply(y, out))
     g = NMullerGraph([op], [y], [out])
     t_graph = clock(g.launch)
+    # the 64 right-hand sides split over copies of the operator, one graph
+    # branch per copy: the small applies run side by side
+    ncopy = 8
+    copies = [op] + [NMullerOperator(s, 1.0, 2.25, tol=1e-4, precision=B.IFGF_FP32, max_nrhs=64 // ncopy)
+                     for _ in range(ncopy - 1)]
+    per = 64 // ncopy
+    gb = NMullerGraph(copies, [y[i * per:(i + 1) * per] for i in range(ncopy)],
+                      [out[i * per:(i + 1) * per] for i in range(ncopy)])
+    t_branch = clock(gb.launch)
+    ref = torch.empty_like(out)
+    for i in range(64):
+        op.apply(y[i:i + 1], ref[i:i + 1])
+    gb.launch()
+    torch.cuda.synchronize()
+    branch_dev = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
     res = {"workload": "config-1 sphere (1,536 points), 64 RHS, mixed form",
            "rhs_matvecs_per_s_looped": 64 / t_loop, "rhs_matvecs_per_s_batched": 64 / t_batch,
            "rhs_matvecs_per_s_graph": 64 / t_graph, "graph_nodes": g.nodes, "autotuned_columns": cols,
-           "ms_looped": t_loop * 1e3, "ms_batched": t_batch * 1e3, "ms_graph": t_graph * 1e3}
+           "rhs_matvecs_per_s_graph_branches": 64 / t_branch, "graph_branches": ncopy,
+           "graph_branches_vs_looped": t_loop / t_branch, "graph_branches_rel_dev": branch_dev,
+           "ms_looped": t_loop * 1e3, "ms_batched": t_batch * 1e3, "ms_graph": t_graph * 1e3,
+           "ms_graph_branches": t_branch * 1e3}
+    gb.close()
+    for c in copies[1:]:
+        c.close()
     g.close()
     # GMRES for 64 plane waves (directions uniform on the sphere, polarisations
     # uniform in the tangent plane): lock-step batch vs one solve at a time
@@ -196,11 +217,15 @@ def batching(log, reps=5):
     return res
 
 
-def bodies32(log, reps=5):
-    """32 uneven ellipsoids (a, b, c ~ U[0.5, 3], eps_r ~ U[1.5, 4], seeds
-    1000 + i; patches per face ceil(sqrt(A / 1.5)) for surface area A, so a
-    patch is about (0.5 wavelengths)^2; 10 x 10 nodes), mixed form: 32 looped
-    applies vs one graph launch of all 32.  The host plans take minutes."""
+def bodies32(log, reps=5, check=True):
+    """Config 3b: 32 uneven ellipsoids (a, b, c ~ U[0.5, 3], eps_r ~ U[1.5, 4],
+    seeds 1000 + i; patches per face ceil(sqrt(A / 1.5)) for surface area A, so
+    a patch is about (0.5 wavelengths)^2; 10 x 10 nodes), mixed form: 32
+    looped applies vs one graph launch in which every body is a branch of its
+    own (the bodies share nothing, so they run side by side).  The graph's
+    outputs are compared with the looped ones, and A y of the 4 smallest
+    bodies with the oracle's O1 forward map on 3 random patches each."""
+    import numpy as np
     import torch
     import synth
     from paper_2408_02274_amd import NMullerGraph, NMullerOperator
@@ -209,7 +234,7 @@ def bodies32(log, reps=5):
     def area(a, b, c, p=1.6075):   # Knud Thomsen's approximation
         return 4 * math.pi * (((a * b) ** p + (a * c) ** p + (b * c) ** p) / 3) ** (1 / p)
 
-    ops, ys, outs, npts = [], [], [], []
+    ops, ys, outs, npts, specs = [], [], [], [], []
     t0 = time.perf_counter()
     for i, (a, b, c, eps) in enumerate(synth.ellipsoid_batch(32, 1000)):
         npf = max(1, math.ceil(math.sqrt(area(a, b, c) / 1.5)))
@@ -218,8 +243,9 @@ def bodies32(log, reps=5):
         ys.append(torch.from_numpy(synth.complex_normal((1, 4, s.n), 100 + i)).to("cuda"))
         outs.append(torch.empty_like(ys[-1]))
         npts.append(s.n)
-        log(f"body {i}: n = {s.n}, plans {time.perf_counter() - t0:.0f} s")
+        specs.append((a, b, c, eps, npf))
     plan_s = time.perf_counter() - t0
+    log(f"bodies32: {sum(npts)} points, plans {plan_s:.0f} s")
 
     def clock(fn):
         fn()
@@ -231,13 +257,36 @@ def bodies32(log, reps=5):
         return (time.perf_counter() - t) / reps
 
     t_loop = clock(lambda: [op.apply(y, o) for op, y, o in zip(ops, ys, outs)])
+    looped = [o.clone() for o in outs]
     g = NMullerGraph(ops, ys, outs)
     t_graph = clock(g.launch)
+    dev = max(float(torch.linalg.norm(o - r) / torch.linalg.norm(r)) for o, r in zip(outs, looped))
     res = {"workload": "32 ellipsoids, seeds 1000..1031, mixed form", "points_total": int(sum(npts)),
            "points_min": int(min(npts)), "points_max": int(max(npts)), "plan_seconds": plan_s,
            "ms_looped": t_loop * 1e3, "ms_graph": t_graph * 1e3, "batch_matvecs_per_s_graph": 1 / t_graph,
-           "body_matvecs_per_s_graph": 32 / t_graph, "graph_nodes": g.nodes}
+           "body_matvecs_per_s_graph": 32 / t_graph, "body_matvecs_per_s_looped": 32 / t_loop,
+           "graph_vs_looped": t_loop / t_graph, "graph_branches": 32, "graph_nodes": g.nodes,
+           "graph_vs_looped_rel_dev": dev,
+           "note": "one graph launch with one branch per body (fork/join), not a persistent kernel"}
     g.close()
+    if check:
+        import tempfile
+        import subprocess
+        nproc = min(16, os.cpu_count() or 1)
+        err = {}
+        for i in sorted(range(32), key=lambda j: npts[j])[:4]:
+            a, b, c, eps, npf = specs[i]
+            o = os.path.join(tempfile.mkdtemp(), "o1.npz")
+            cmd = [sys.executable, "-m", "oracle.sample", "--geometry", "ellipsoid",
+                   "--axes", ",".join(repr(float(v)) for v in (a, b, c)), "--npf", str(npf), "--nc", "10",
+                   "--eps-e", "1.0", "--eps-i", repr(float(eps)), "--npatch", "3", "--y-seed", str(100 + i),
+                   "--nproc", str(min(nproc, 3)), "--out", o]
+            subprocess.run(cmd, cwd=ROOT, check=True, timeout=1200)
+            o1 = dict(np.load(o))
+            g_ay = looped[i].cpu().numpy()[0][:, o1["rows"]]
+            err[f"body {i} ({npts[i]} points)"] = float(np.linalg.norm(g_ay - o1["Ay"]) / np.linalg.norm(o1["Ay"]))
+        res["err_vs_o1_Ay"] = err
+        res["err_rows"] = "A y on the nodes of 3 random patches (seed 2) of each of the 4 smallest bodies"
     for op in ops:
         op.close()
     log(f"bodies32: {res}")
@@ -279,43 +328,61 @@ def waveguide(args, log):
     """The large workload shaped like the paper's waveguide example (Sec. IV):
     rounded rectangular box 40 x 1 x 0.5 wavelengths with edge radius 0.1,
     patches of about 0.087 wavelengths with 10 x 10 nodes (16,704 patches,
-    1,670,400 points), eps 12.1 inside and 2.1 outside (k_int = 21.86, k_ext =
-    9.105).  Timed: one evaluation of the IFGF sums (16 S + 12 n.grad S at both
-    wavenumbers, the T_IFGF part of the paper's forward map) in FP32 with
-    FP32-sized workspaces, tol 1e-4; the error against the oracle's direct sums
-    on 4,096 random nodes; device memory of the plan.  The N-Mueller corrections
-    of this surface (about 1.6e9 (target, node) pairs at 64 bytes in FP64) do
-    not fit one GPU beside the cone buffers and are not built here."""
+    1,670,400 points, 6,681,600 unknowns), eps 12.1 inside and 2.1 outside
+    (k_int = 21.86, k_ext = 9.105), excited by an electric dipole y-polarised
+    at the complex source point (-20.5, 0, 0) + i b x (b = k_ext w0^2 / 2,
+    w0 = 0.4): a Gaussian beam launched into the end face x = -20.
+    Timed: N-Mueller matvecs in the mixed form (FP32 IFGF with FP32-sized
+    workspaces, FP64 near-field corrections built on the device, FP64
+    assembly), and flexible GMRES(80) with M = D^-1 to a 1e-4 residual.  The
+    residuals come from the mixed operator: beside 132 GiB of FP64
+    corrections the FP64 IFGF form does not fit.  GMRES runs one restart cycle per call (the next call starts from
+    the last iterate), which keeps progress lines coming and costs one extra
+    residual matvec per cycle.  Checked: the IFGF sums and A y against the
+    oracle's O1 forward map on the nodes of --oracle-patches-wg random
+    patches; device memory."""
     import numpy as np
     import torch
     import synth
-    from paper_2408_02274_amd import IFGFPlan
+    from paper_2408_02274_amd import NMullerOperator
     from paper_2408_02274_amd import binding as B
-    surf = synth.rounded_box((20.0, 0.5, 0.25), 0.1, 0.087, 10)
-    ks = (2 * math.pi * math.sqrt(12.1), 2 * math.pi * math.sqrt(2.1))
-    area = 8 * (20 * 0.5 + 20 * 0.25 + 0.5 * 0.25)            # outer box; the rounding removes < 1%
-    wconst = area / surf.n
+    geo = {"half": (20.0, 0.5, 0.25), "edge": 0.1, "side": 0.087, "nc": 10}
+    surf = synth.rounded_box(geo["half"], geo["edge"], geo["side"], geo["nc"])
+    eps_e, eps_i = 2.1, 12.1
+    omega = 2 * math.pi
+    ke = omega * math.sqrt(eps_e)
     free0 = torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
-    plan = IFGFPlan(surf.x, surf.normal, np.full(surf.n, wconst), ks[0], ks[1], 1e-4,
-                    precision=B.IFGF_FP32, fp32_workspaces=1, verbose=1)
+    op = NMullerOperator(surf, eps_e, eps_i, tol=args.tol, precision=B.IFGF_FP32, fp32_workspaces=1, verbose=1)
     plan_s = time.perf_counter() - t0
     free1 = torch.cuda.mem_get_info()[0]
-    log(f"waveguide plan: n = {surf.n}, {plan_s:.1f} s, {(free0 - free1) / 2**30:.1f} GiB on the device")
-    phi = torch.from_numpy(synth.complex_normal((1, 8, surf.n), 3)).to("cuda")
-    out = torch.empty((1, 2, 14, surf.n), dtype=torch.complex128, device="cuda")
+    info = op.plan_info()
+    ih = op.ifgf_handle()
+    st0 = B.ifgf_stats(ih)
+    log(f"waveguide plan: n = {surf.n}, {plan_s:.1f} s, {(free0 - free1) / 2**30:.1f} GiB on the device; "
+        f"corrections {info}")
+    stream = torch.cuda.current_stream()
+    y = torch.from_numpy(synth.complex_normal((1, 4, surf.n), 2)).to("cuda")
+    out = torch.empty_like(y)
     for _ in range(args.warmup):
-        plan.apply(phi, out)
+        op.apply(y, out, stream=stream.cuda_stream)
     torch.cuda.synchronize()
-    plan.set_timing(True)
+    B.ifgf_set_timing(ih, True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan.apply(phi, out)
+        op.apply(y, out, stream=stream.cuda_stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    st = plan.stats()
-    plan.set_timing(False)
-    g = out.cpu().numpy()[0]
+    st = B.ifgf_stats(ih)
+    B.ifgf_set_timing(ih, False)
+    log(f"{args.steps} matvecs in {el:.2f} s")
+    Ay = out.cpu().numpy()[0]
+    phi = torch.from_numpy(synth.complex_normal((1, 8, surf.n), 3)).to("cuda")
+    sd = torch.empty((1, 2, 14, surf.n), dtype=torch.complex128, device="cuda")
+    B.ifgf_apply(ih, phi, 1, sd)
+    torch.cuda.synchronize()
+    SD = sd.cpu().numpy()[0]
+    del phi, sd, y, out
     npts = st["Ps"] * st["Pa"] * st["Pa"]
     kern = kernel_table(st, args.steps, npts)
     dom = max(kern, key=lambda k: kern[k]["ms"])
@@ -324,45 +391,105 @@ def waveguide(args, log):
     roof = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK["fp32_mfma"] / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK["fp32_mfma"], "traffic": None,
             "avg_launch_ms": d["ms"] / d["launches"], "flop_per_launch": d["flop"] / d["launches"]}
-    res = {"metric": "IFGF sums evaluations/s (T_IFGF part of the N-Mueller forward map)",
-           "value": args.steps / el, "unit": "evaluations/s", "n_gpus": 1, "steps": args.steps,
+
+    # excitation and GMRES
+    pts = torch.from_numpy(np.ascontiguousarray(surf.x)).to("cuda")
+    w0 = 0.4
+    beam = (ke * w0 * w0 / 2, 0.0, 0.0)
+    E, H = B.ifgf_dipole_field(pts, ke, eps_e, omega, (0.0, 1.0, 0.0), (-20.5, 0.0, 0.0), beam)
+    b = op.rhs(E.unsqueeze(0), H.unsqueeze(0))
+    del E, H, pts
+    torch.cuda.empty_cache()           # the solver allocates its bases outside torch's cache
+    # flexible GMRES with M = D^-1 (the identity part of eq. n_muller, which
+    # differs by (eps_e + eps_i) / 2 = 7.1 between the two rows here)
+    nq = 100
+    dims = [8 * nq + 4, 256, 256, 8 * nq]
+    op.set_preconditioner(np.zeros(sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(3)), np.float32), dims)
+    restart = 80
+    ysol = torch.zeros_like(b)
+    iters, t_gm, cycles, last = 0, 0.0, 0, None
+    while iters < args.maxit:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ysol, inf = op.solve(b, y=ysol, rtol=1e-4, maxit=min(restart, args.maxit - iters), restart=restart)
+        torch.cuda.synchronize()
+        t_gm += time.perf_counter() - t0
+        last = inf[0]
+        iters += last["iters"]
+        cycles += 1
+        log(f"GMRES cycle {cycles}: {iters} iterations, residual {last['true_relres']:.3e}, {t_gm:.1f} s")
+        if last["converged"] or last["iters"] == 0:
+            break
+    gm = {"seconds": t_gm, "iters": iters, "true_relres": last["true_relres"], "converged": last["converged"],
+          "solver": f"flexible GMRES({restart}), M = D^-1", "cycles": cycles,
+          "residual_fp64": last["residual_fp64"],
+          "residual_form": "mixed operator (FP32 IFGF, FP64 corrections and assembly), FP64 arithmetic"}
+    ynorm = float(torch.linalg.norm(ysol))
+    del ysol, b
+    peak_gib = (free0 - torch.cuda.mem_get_info()[0]) / 2**30
+    op.close()
+    res = {"metric": METRIC, "value": args.steps / el, "unit": "matvecs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"rounded box 40 x 1 x 0.5 wavelengths, edge radius 0.1, {surf.P} patches x "
-                                  f"10 x 10 nodes ({surf.n} points), k_int = {ks[0]:.3f}, k_ext = {ks[1]:.3f}, "
-                                  f"IFGF tol 1e-4, FP32 cone grids and FP32-sized workspaces",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"N-Mueller forward map, rounded box 40 x 1 x 0.5 wavelengths, edge radius 0.1, "
+                                  f"{surf.P} patches x 10 x 10 nodes ({surf.n} points, {4 * surf.n} unknowns), "
+                                  f"eps 12.1 inside / 2.1 outside (k_int = {omega * math.sqrt(eps_i):.3f}, "
+                                  f"k_ext = {ke:.3f}), IFGF tol {args.tol}, complex-source-point dipole RHS; "
+                                  f"mixed: FP32 IFGF with FP32-sized workspaces, FP64 corrections/assembly/GMRES",
                       "Ps": st["Ps"], "Pa": st["Pa"], "D": st["D"], "plan_seconds": round(plan_s, 1),
-                      "device_GiB": round((free0 - free1) / 2**30, 2), "plan_device_bytes": st["device_bytes"]},
+                      "corrections_seconds": round(info["corrections_seconds"], 2),
+                      "corrections_on_device": info["corrections_on_device"],
+                      "correction_pairs": info["correction_pairs"],
+                      "correction_GiB": round(info["correction_bytes"] / 2**30, 2),
+                      "ifgf_cone_buffer_GiB": round(st0.get("cone_buffer_bytes", 0) / 2**30, 2),
+                      "ifgf_target_result_GiB": round(st0.get("target_result_bytes", 0) / 2**30, 2),
+                      "plan_device_GiB": round((free0 - free1) / 2**30, 2),
+                      "peak_device_GiB": round(peak_gib, 2)},
+           "gmres_time_to_1e-4_s": t_gm if last["converged"] else None,
+           "gmres": gm, "solution_norm": ynorm,
            "roofline": roof,
            "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in kern.items()},
-           "paper_context": "Table I row 5 (1,572,864 points): T_IFGF 50.14 s on 128 EPYC 7763 cores"}
-    plan.close()
+           "paper_context": "Table I row 5 (1,572,864 points): T_IFGF 50.14 s, forward map 58.14 s on 128 "
+                            "EPYC 7763 cores"}
     if not args.no_cpu:
         import tempfile
         import subprocess
         nproc = min(16, os.cpu_count() or 1)
         o = os.path.join(tempfile.mkdtemp(), "o1.npz")
         cmd = [sys.executable, "-m", "oracle.sample", "--geometry", "rounded_box", "--nc", "10",
-               "--direct-rows", "4096", "--k-int", repr(ks[0]), "--k-ext", repr(ks[1]),
-               "--weight", repr(wconst), "--nproc", str(nproc), "--out", o]
+               "--half", ",".join(repr(v) for v in geo["half"]), "--edge", repr(geo["edge"]),
+               "--side", repr(geo["side"]), "--eps-e", repr(eps_e), "--eps-i", repr(eps_i),
+               "--npatch", str(args.oracle_patches_wg), "--nproc", str(nproc), "--out", o]
+        t0 = time.perf_counter()
         subprocess.run(cmd, cwd=ROOT, check=True, timeout=1200)
+        log(f"oracle sample ({args.oracle_patches_wg} patches) in {time.perf_counter() - t0:.1f} s")
         o1 = dict(np.load(o))
         rows = o1["rows"]
-        gs = g[:, :, rows]
 
         def rel(a, b):
             return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
-        res["err_vs_o1"] = {"S": max(rel(gs[q, :8], o1["SD"][q, :8]) for q in range(2)),
-                            "D": max(rel(gs[q, 8:], o1["SD"][q, 8:]) for q in range(2)),
-                            "rows": "4096 random nodes (seed 2), densities from seed 3"}
-        t = float(o1["seconds_direct"])
+        gs = SD[:, :, rows]
+        err = {"S": max(rel(gs[q, :8], o1["SD"][q, :8]) for q in range(2)),
+               "D": max(rel(gs[q, 8:], o1["SD"][q, 8:]) for q in range(2)),
+               "Ay": rel(Ay[:, rows], o1["Ay"]),
+               "rows": f"{rows.size} points of {len(o1['patches'])} patches drawn from seed 2 ({4 * rows.size} "
+                       f"rows of A y); S, D: IFGF sums of densities from seed 3 vs direct sums; A y: unknowns "
+                       f"from seed 2 vs the oracle's forward map"}
+        err["within_tol"] = all(err[k] <= args.tol for k in ("S", "D", "Ay"))
+        res["err_vs_o1"] = err
+        t_rows = float(o1["seconds_forward"])
+        per_matvec = t_rows * surf.n / rows.size
         res["cpu_baseline"] = {
-            "value": rows.size / (t * surf.n), "unit": "evaluations/s", "cores": nproc, "kind": "oracle",
-            "sample": f"oracle O1 direct sums (S and n.grad S, 8 densities x 2 wavenumbers) on {rows.size} of "
-                      f"{surf.n} nodes took {t:.1f} s over {nproc} worker processes; extrapolated "
-                      f"x{surf.n / rows.size:.0f} to one evaluation", "cpu_model": cpu_model()}
-        log(f"waveguide errors vs O1: {res['err_vs_o1']}")
+            "value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": int(o1["nproc"]), "kind": "oracle",
+            "sample": f"oracle O1 forward map (direct regular sums, singular corrections, assembly) on "
+                      f"{rows.size} of {surf.n} points ({4 * rows.size} rows) took {t_rows:.1f} s over "
+                      f"{int(o1['nproc'])} worker processes (one BLAS thread each); extrapolated "
+                      f"x{surf.n / rows.size:.0f} to one matvec",
+            "gmres_seconds_estimated": per_matvec * iters,
+            "gmres_note": "estimated: O1 matvec time x the GPU's GMRES iteration count",
+            "cpu_model": cpu_model(), "nproc_host": os.cpu_count()}
+        log(f"waveguide errors vs O1: {err}")
     return res
 
 
@@ -388,6 +515,8 @@ def main():
     ap.add_argument("--npf", type=int, default=16, help="patches per cube face edge")
     ap.add_argument("--nc", type=int, default=10, help="Chebyshev nodes per patch direction")
     ap.add_argument("--radius", type=float, default=5.0)
+    ap.add_argument("--oracle-patches-wg", type=int, default=11,
+                    help="patches of the waveguide sampled by the oracle (100 nodes each)")
     ap.add_argument("--oracle-patches", type=int, default=41,
                     help="patches whose nodes the oracle evaluates (41 x 100 points at the default size)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -400,9 +529,10 @@ def main():
     ap.add_argument("--ifgf-only", action="store_true",
                     help="time the raw IFGF sums only (no N-Mueller plan: seconds to set up)")
     ap.add_argument("--waveguide", action="store_true",
-                    help="the 1.67M-point rounded-box waveguide workload instead (IFGF sums; ~6 minutes)")
-    ap.add_argument("--bodies32", action="store_true",
-                    help="also time the 32-ellipsoid batch (host plans take ~5 minutes)")
+                    help="the 1.67M-point rounded-box waveguide workload instead (N-Mueller matvecs and "
+                         "GMRES with the dipole excitation; ~10 minutes)")
+    ap.add_argument("--no-bodies32", action="store_true",
+                    help="skip the 32-ellipsoid batch (config 3b; its plans and oracle checks take ~2 minutes)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -596,8 +726,8 @@ def main():
     }
     if not args.no_batch and not args.ifgf_only:
         res["batching"] = batching(log)
-    if args.bodies32:
-        res["bodies32"] = bodies32(log)
+    if not args.no_bodies32 and not args.ifgf_only:
+        res["bodies32"] = bodies32(log, check=not args.no_cpu)
     if not args.no_cpu and not args.ifgf_only:
         # the oracle (O1) on the nodes of args.oracle_patches patches, and the
         # Mie error of the mixed GMRES solution, in the oracle's own program

@@ -79,7 +79,18 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  *   interpolant times the centred factor; IFGF_DERIV_FD is the paper's
  *   (G F)(x + h n) - (G F)(x) over h = 1e-6, x + h n interpolated in the cone
  *   of x.  FD needs IFGF_FP64, the matrix-core orders and one right-hand side
- *   per apply (max_nrhs = batch_columns = 1); near sums stay analytic.      */
+ *   per apply (max_nrhs = batch_columns = 1); near sums stay analytic.
+ * target_chunk_pairs: the matrix-core target interpolation writes one result
+ *   per (target, cousin box) pair and sums them per target; it takes the
+ *   targets of a level in chunks of consecutive targets holding at most this
+ *   many pairs, so that the result buffer stays bounded (0 -> 1 GiB of FP64
+ *   results, 2,396,745 pairs; the sums do not depend on it).
+ * plan_on_device: 1 builds the plan tables (algorithm step 1: Morton order,
+ *   boxes, neighbours, cousins, relevant cones, pair and tile lists) with
+ *   kernels on the current device instead of the host; the tables are the
+ *   same (ignored with host_only).
+ * keep_pair_tables: 1 keeps host copies of the cousin-pair and
+ *   propagation-pair cone slots after upload, for ifgf_plan_table.         */
 typedef struct {
   int Ps, Pa;
   int ns_init, na_init;
@@ -92,6 +103,9 @@ typedef struct {
   int fp32_workspaces;
   int verbose;
   int deriv_mode;
+  int64_t target_chunk_pairs;
+  int plan_on_device;
+  int keep_pair_tables;
 } ifgf_options;
 
 void ifgf_default_options(ifgf_options* opt);
@@ -111,7 +125,13 @@ void ifgf_default_options(ifgf_options* opt);
  *           orders whose relative L2 error (with refine_radial = 1) stayed
  *           below tol in every output block (S and the normal-derivative
  *           sums separately) on spheres of radius 1 to 5 wavelengths and an
- *           ellipsoid; below 1e-6 the largest orders do not reach tol
+ *           ellipsoid, and on the 40 x 1 x 0.5-wavelength rounded box at
+ *           1.67M points (S 2.5e-6, D 3.8e-5 at tol 1e-4).  The mapping is
+ *           empirical, not a bound: on the same box with only 11,360 points
+ *           and random weights the normal-derivative sums reached 2.5e-4 at
+ *           tol 1e-4 (they are small against the terms they sum there; the
+ *           next orders bring them to 3.2e-5).  Below 1e-6 the largest orders
+ *           do not reach tol
  *  opt      NULL = defaults
  * Errors: IFGF_EINVAL (bad sizes, NaN/Inf, non-unit normals, weights <= 0,
  * k <= 0, tol out of range, duplicate points), IFGF_ENOMEM, IFGF_EHIP.     */
@@ -164,6 +184,11 @@ int ifgf_autotune(ifgf_plan_t plan, void* stream, int* chosen);
  * available when Pa = 5 or 6 and 3 <= Ps <= 6 (else IFGF_EINVAL).  Used by the
  * mixed-precision solve: Arnoldi on the FP32 form, residuals on the FP64.   */
 int ifgf_set_precision(ifgf_plan_t plan, int precision, int* previous);
+
+/* The working precisions a built plan can run: bit 0 IFGF_FP64 (not for
+ * plans built with fp32_workspaces), bit 1 IFGF_FP32 (matrix-core orders and
+ * analytic derivative).  0 for NULL or host_only plans.                     */
+int ifgf_precisions(ifgf_plan_t plan);
 
 /* Device-side failures.  The FP32 propagation adds its tiles into a shared
  * accumulator under a lock whose wait is bounded; a wavefront that gives up
@@ -241,7 +266,11 @@ typedef struct nmuller_s* nmuller_t;
  *   delta_p = delta_factor x diagonal of the patch's node bounding box
  *   (Sec. III-B eq. patch_sing; 0 -> 1.0).
  * nbeta: Fejer points per direction of the singular rule (eq. int_moments_cov;
- *   0 -> 6 Nc).  d_cov: parameter d of the sigmoidal map (eq. mk_cov_1; 4).  */
+ *   0 -> 6 Nc).  d_cov: parameter d of the sigmoidal map (eq. mk_cov_1; 4).
+ * corrections_on_host: 0 (default) builds the corrections on the device when
+ *   Nc is 4, 5, 6, 8 or 10 and nbeta <= 64 (the same pairs and closest points
+ *   as the host builder, bit for bit; weights equal to FP64 rounding), else on
+ *   the host; 1 always builds them on the host.                             */
 typedef struct {
   int P, Nc;
   double eps_e, eps_i, mu_e, mu_i;
@@ -249,6 +278,7 @@ typedef struct {
   double delta_factor;
   int nbeta;
   int d_cov;
+  int corrections_on_host;
 } nmuller_params;
 
 void nmuller_default_params(nmuller_params* p);
@@ -295,20 +325,30 @@ int nmuller_geometry(nmuller_t nm, int which, double* buf, int64_t cap);
 /* Near-field corrections: npairs receives the number of (target, patch)
  * pairs; row_off [n+1], pair_patch [npairs] and vals [npairs][4][Nc^2][2]
  * (kernel order S k_int, S k_ext, D k_int, D k_ext; FP64 re/im) are filled
- * when non-NULL.  vals are available from host_only plans only.             */
+ * when non-NULL (vals copied from the device when the plan holds them
+ * there only).                                                              */
 int nmuller_corrections(nmuller_t nm, int64_t* npairs, int64_t* row_off,
                         int32_t* pair_patch, double* vals);
+
+/* Plan facts, info[0..3]: 1 if the corrections were built on the device,
+ * seconds the correction build took, number of (target, patch) pairs, bytes
+ * of correction weights.  cap >= 4.                                         */
+int nmuller_plan_info(nmuller_t nm, double* info, int cap);
 
 /* Per right-hand side outcome of nmuller_solve.                             */
 typedef struct {
   int iters;              /* matrix-vector products in the Arnoldi process     */
   int converged;          /* 1 when true_relres <= rtol                        */
-  double true_relres;     /* ||b - A y|| / ||b|| from a final FP64 matvec      */
+  double true_relres;     /* ||b - A y|| / ||b|| from a final matvec           */
   double arnoldi_relres;  /* GMRES residual estimate at exit                   */
   double seconds;         /* host wall time from the start of its lock-step
                              group until this right-hand side finished        */
   int precond_iters;      /* iterations run with the network part of M on      */
   int fallbacks;          /* preconditioned cycles abandoned (see below)       */
+  int residual_fp64;      /* 1: residuals from the FP64 IFGF form; 0: from the
+                             working form, for plans that hold no FP64 cone
+                             buffers (fp32_workspaces); corrections, assembly
+                             and the residual arithmetic are FP64 either way */
 } ifgf_solve_info;
 
 /* Solve A y = b by GMRES (Sec. III-A eq. lin_system): Arnoldi in FP64 with
@@ -446,9 +486,13 @@ void mlp_destroy(mlp_t net);
  * ------------------------------------------------------------------------- */
 typedef struct ifgf_graph_s* ifgf_graph_t;
 
-/* Capture nmuller_apply(ops[i], y[i], nrhs[i], Ay[i]) for i < nops, in that
- * order, on a private stream.  y[i], Ay[i] device [nrhs[i]][4][n_i] complex
- * FP64.  Per-kernel timing must be off on every operator (IFGF_EINVAL).    */
+/* Capture nmuller_apply(ops[i], y[i], nrhs[i], Ay[i]) for i < nops.  The
+ * applies of one operator stay in the given order on one branch of the
+ * graph (they share its workspaces); different operators share nothing and
+ * get branches of their own, forked from and joined into the launch
+ * stream, so they may run concurrently.  y[i], Ay[i] device
+ * [nrhs[i]][4][n_i] complex FP64; outputs of different entries must not
+ * overlap.  Per-kernel timing must be off on every operator (IFGF_EINVAL). */
 int nmuller_graph_capture(ifgf_graph_t* out, int nops, const nmuller_t* ops,
                           const void* const* y, const int* nrhs, void* const* Ay);
 /* Enqueue one replay on `stream`.                                           */

@@ -22,15 +22,19 @@ NS = 8   # densities with S
 ND = 6   # densities with D
 
 
-def regular_sums(x, normals, weights, phi, kappas, targets=None, block=256):
+def regular_sums(x, normals, weights, phi, kappas, targets=None, block=None):
     """Direct regular sums.
 
     x [N,3], normals [N,3], weights [N], phi [8,N] complex (unweighted),
     kappas (k0, k1).  targets: optional index array of target points (the
     self term excluded is the target's own index).  Returns [2,14,T].
+    Targets are taken `block` at a time (default: about 2^24 target-source
+    pairs per block, which bounds the temporaries to a few GB).
     """
     x = np.asarray(x, dtype=np.float64)
     N = x.shape[0]
+    if block is None:
+        block = max(1, min(256, (1 << 24) // max(N, 1)))
     a = np.asarray(phi) * np.asarray(weights)[None, :]
     tgt = np.arange(N) if targets is None else np.asarray(targets)
     out = np.zeros((2, NS + ND, tgt.size), dtype=np.complex128)

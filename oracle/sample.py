@@ -4,8 +4,8 @@ process pool over the host cores (oracle; test infrastructure only).
 Run as a separate program (python -m oracle.sample ...) so that its worker
 processes never share a process with device work.  For a cube-sphere of
 radius R (6 npf^2 patches of Nc x Nc nodes, the geometry of the paper's
-sphere runs, Sec. IV) it computes, on the nodes of `npatch` patches drawn
-from `seed`:
+sphere runs, Sec. IV), an ellipsoid of the uneven batch or the rounded box
+of its waveguide example, it computes, on the nodes of `npatch` patches drawn from `seed`:
 
   * the direct regular sums S_q[phi_k], D_q[phi_k] of O1 (eq. ifgf_sum_em,
     self term excluded) for i.i.d. complex normal densities phi (seed
@@ -41,6 +41,8 @@ def _surface(geom):
     import synth
     if geom["kind"] == "sphere":
         return synth.cube_sphere(geom["npf"], geom["nc"], geom["radius"])
+    if geom["kind"] == "ellipsoid":
+        return synth.ellipsoid(*geom["axes"], geom["npf"], geom["nc"])
     return synth.rounded_box(geom["half"], geom["edge"], geom["side"], geom["nc"])
 
 
@@ -67,7 +69,7 @@ def _forward_rows(chunk):
     t0 = time.perf_counter()
     nm = nmuller.NMuller(surf, _W["eps"][0], _W["eps"][1], patches=list(chunk))
     ay = nm.apply(_W["y"])
-    sd = direct.regular_sums(surf.x, surf.n, surf.w, _W["phi"], nm.kappas, targets=nm.rows, block=64)
+    sd = direct.regular_sums(surf.x, surf.n, surf.w, _W["phi"], nm.kappas, targets=nm.rows)
     return nm.rows, ay, sd, time.perf_counter() - t0
 
 
@@ -91,7 +93,8 @@ def _field_points(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--geometry", default="sphere", choices=["sphere", "rounded_box"])
+    ap.add_argument("--geometry", default="sphere", choices=["sphere", "rounded_box", "ellipsoid"])
+    ap.add_argument("--axes", default="1,1,1", help="ellipsoid: semi-axes a,b,c")
     ap.add_argument("--npf", type=int, default=0)
     ap.add_argument("--nc", type=int, required=True)
     ap.add_argument("--radius", type=float, default=1.0)
@@ -113,9 +116,13 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     from multiprocessing import get_context
-    geom = ({"kind": "sphere", "npf": a.npf, "nc": a.nc, "radius": a.radius} if a.geometry == "sphere" else
-            {"kind": "rounded_box", "half": tuple(float(v) for v in a.half.split(",")), "edge": a.edge,
-             "side": a.side, "nc": a.nc})
+    if a.geometry == "sphere":
+        geom = {"kind": "sphere", "npf": a.npf, "nc": a.nc, "radius": a.radius}
+    elif a.geometry == "ellipsoid":
+        geom = {"kind": "ellipsoid", "axes": tuple(float(v) for v in a.axes.split(",")), "npf": a.npf, "nc": a.nc}
+    else:
+        geom = {"kind": "rounded_box", "half": tuple(float(v) for v in a.half.split(",")), "edge": a.edge,
+                "side": a.side, "nc": a.nc}
     res = {}
     ctx = get_context("spawn")
     with ctx.Pool(a.nproc, initializer=_init,
@@ -131,7 +138,7 @@ def main(argv=None):
             res["SD"] = np.concatenate([p[0] for p in parts], axis=2)
             res["n"] = n
         elif a.npatch > 0:
-            P = 6 * a.npf * a.npf
+            P = _surface(geom).P
             patches = np.sort(np.random.default_rng(a.seed).choice(P, a.npatch, replace=False))
             res["patches"] = patches
             t0 = time.perf_counter()

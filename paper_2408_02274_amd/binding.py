@@ -34,19 +34,21 @@ class Options(C.Structure):
                 ("refine_radial", C.c_int), ("leaf_wavelengths", C.c_double),
                 ("precision", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int),
                 ("batch_columns", C.c_int), ("fp32_workspaces", C.c_int), ("verbose", C.c_int),
-                ("deriv_mode", C.c_int)]
+                ("deriv_mode", C.c_int), ("target_chunk_pairs", C.c_int64), ("plan_on_device", C.c_int),
+                ("keep_pair_tables", C.c_int)]
 
 
 class NMullerParams(C.Structure):
     _fields_ = [("P", C.c_int), ("Nc", C.c_int), ("eps_e", C.c_double), ("eps_i", C.c_double),
                 ("mu_e", C.c_double), ("mu_i", C.c_double), ("omega", C.c_double),
-                ("delta_factor", C.c_double), ("nbeta", C.c_int), ("d_cov", C.c_int)]
+                ("delta_factor", C.c_double), ("nbeta", C.c_int), ("d_cov", C.c_int),
+                ("corrections_on_host", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("true_relres", C.c_double),
                 ("arnoldi_relres", C.c_double), ("seconds", C.c_double),
-                ("precond_iters", C.c_int), ("fallbacks", C.c_int)]
+                ("precond_iters", C.c_int), ("fallbacks", C.c_int), ("residual_fp64", C.c_int)]
 
 
 _lib = None
@@ -74,6 +76,8 @@ def lib():
         L.ifgf_set_timing.argtypes = [vp, ci]
         L.ifgf_set_timing.restype = ci
         L.ifgf_set_precision.argtypes = [vp, ci, C.POINTER(ci)]
+        L.ifgf_precisions.argtypes = [vp]
+        L.ifgf_precisions.restype = ci
         L.ifgf_autotune.argtypes = [vp, vp, C.POINTER(ci)]
         L.ifgf_check.argtypes = [vp, vp, C.POINTER(C.c_uint)]
         L.ifgf_dipole_field.argtypes = [i64, vp, dbl, dbl, dbl, vp, vp, vp, vp]
@@ -104,6 +108,7 @@ def lib():
         L.nmuller_rhs.argtypes = [vp, vp, vp, ci, vp, vp]
         L.nmuller_geometry.argtypes = [vp, ci, vp, i64]
         L.nmuller_corrections.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
+        L.nmuller_plan_info.argtypes = [vp, vp, ci]
         L.nmuller_solve.argtypes = [vp, vp, ci, vp, ci, dbl, ci, ci, C.POINTER(SolveInfo), vp]
         L.nmuller_solve_noalloc.argtypes = [vp, vp, vp, ci, dbl, ci, ci, C.POINTER(SolveInfo), vp]
         L.nmuller_solve_noalloc.restype = ci
@@ -137,7 +142,8 @@ def lib():
         L.nmuller_destroy.restype = None
         for name in ("ifgf_plan", "ifgf_apply", "ifgf_plan_counts", "ifgf_plan_table", "ifgf_stats",
                      "nmuller_plan", "nmuller_apply", "nmuller_rhs", "nmuller_geometry",
-                     "nmuller_corrections", "nmuller_set_preconditioner", "nmuller_precond_apply",
+                     "nmuller_corrections", "nmuller_plan_info", "nmuller_set_preconditioner", "ifgf_precisions",
+                     "nmuller_precond_apply",
                      "nmuller_precond_pairs", "nmuller_patch_features", "mlp_create", "mlp_num_params",
                      "mlp_set_params", "mlp_get_params", "mlp_get_grad", "mlp_forward", "mlp_backward",
                      "mlp_adam_step", "mlp_train_step", "nmuller_graph_capture", "ifgf_graph_launch",
@@ -376,7 +382,7 @@ class IFGFPlan:
 
 
 def nmuller_plan(P, Nc, points, du, dv, eps_e, eps_i, mu_e=1.0, mu_i=1.0, omega=2 * np.pi,
-                 tol=1e-4, delta_factor=0.0, nbeta=0, d_cov=0, **opts):
+                 tol=1e-4, delta_factor=0.0, nbeta=0, d_cov=0, corrections_on_host=0, **opts):
     """Build an N-Mueller operator plan; returns an opaque handle (int)."""
     n = P * Nc * Nc
     x = _host_f64(points, (n, 3))
@@ -389,6 +395,7 @@ def nmuller_plan(P, Nc, points, du, dv, eps_e, eps_i, mu_e=1.0, mu_i=1.0, omega=
     prm.delta_factor, prm.nbeta = float(delta_factor), int(nbeta)
     if d_cov:
         prm.d_cov = int(d_cov)
+    prm.corrections_on_host = int(corrections_on_host)
     o = default_options()
     for k, v in opts.items():
         setattr(o, k, v)
@@ -452,7 +459,7 @@ def nmuller_solve_noalloc(nm, rhs, y, use_x0=False, rtol=1e-4, maxit=500, restar
 def _info_dict(i):
     return {"iters": i.iters, "converged": bool(i.converged), "true_relres": i.true_relres,
             "arnoldi_relres": i.arnoldi_relres, "seconds": i.seconds,
-            "precond_iters": i.precond_iters, "fallbacks": i.fallbacks}
+            "precond_iters": i.precond_iters, "fallbacks": i.fallbacks, "residual_fp64": bool(i.residual_fp64)}
 
 
 def nmuller_solve_trajectory(nm, rhs, y, X, R, rtol=1e-4, maxit=500, stride=1, stream=None):
@@ -660,6 +667,13 @@ class NMullerOperator:
 
     def corrections(self, values=True):
         return nmuller_corrections(self.handle, self.n, self.Nc, values)
+
+    def plan_info(self):
+        """Where and how fast the corrections were built, their pair count and bytes."""
+        buf = (C.c_double * 4)()
+        _check(lib().nmuller_plan_info(self.handle, buf, 4), "nmuller_plan_info")
+        return {"corrections_on_device": bool(buf[0]), "corrections_seconds": buf[1],
+                "correction_pairs": int(buf[2]), "correction_bytes": int(buf[3])}
 
     def solve_trajectory(self, b, X, R, rtol=1e-4, maxit=500, stride=1, stream=None):
         import torch

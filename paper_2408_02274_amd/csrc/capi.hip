@@ -87,6 +87,9 @@ struct ifgf_plan_s {
   double2* d_out_s = nullptr;  // [n][28]
   double2* d_vals[2] = {nullptr, nullptr};
   int64_t max_slots = 0;
+  // level d uses cone buffer (D - d) & 1: each is sized for its own levels
+  int64_t par_slots[2] = {0, 0};
+  size_t vals_bytes = 0, res_bytes = 0;
   PhaseTimer timer;
   // matrix-core path (Pa = 5 or 6): K-slot cone layout, FP32 or FP64 cone data
   bool mfma = false;
@@ -96,6 +99,8 @@ struct ifgf_plan_s {
   int rsel = 1;                         // right-hand sides per pass in use (<= rcap)
   std::vector<PropGroups> groups;       // groups[d]: propagation into level d
   std::vector<TargetTiles> ttiles;      // ttiles[d]: target pairs by cone (matrix-core interpolation)
+  // chunks of ttiles[d]: tiles [tc_tile[c], tc_tile[c+1]) hold targets [tc_i0[c], tc_i0[c+1])
+  std::vector<std::vector<int64_t>> tc_tile, tc_i0;
   void* d_res = nullptr;                // per-pair target contributions [pairs][28] complex
   unsigned* d_err = nullptr;            // device error word (bit 0: a propagation lock wait gave up)
   int elem = 8;                         // bytes per real of the cone buffers and density copy
@@ -213,6 +218,9 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->fp32_workspaces = 0;
   opt->verbose = 0;
   opt->deriv_mode = IFGF_DERIV_ANALYTIC;
+  opt->target_chunk_pairs = 0;
+  opt->plan_on_device = 0;
+  opt->keep_pair_tables = 0;
 }
 
 int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* normals,
@@ -254,9 +262,17 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   pp.refine_radial = opt.refine_radial;
   pp.leaf_wavelengths = opt.leaf_wavelengths;
   pp.verbose = opt.verbose;
+  if (opt.target_chunk_pairs < 0) return set_error(IFGF_EINVAL, "target_chunk_pairs must be >= 0");
+  pp.target_chunk_pairs = opt.target_chunk_pairs > 0 ? opt.target_chunk_pairs : kTargetChunkPairs;
   std::string err;
   try {
-    if (build_host_plan(p->host, n, points, normals, weights, k_int, k_ext, pp, err)) {
+    if (opt.plan_on_device && !opt.host_only) {
+      const int prc = build_device_plan(p->host, n, points, normals, weights, k_int, k_ext, pp, err);
+      if (prc) {
+        delete p;
+        return set_error(prc == -2 ? IFGF_EHIP : IFGF_EINVAL, err);
+      }
+    } else if (build_host_plan(p->host, n, points, normals, weights, k_int, k_ext, pp, err)) {
       delete p;
       return set_error(IFGF_EINVAL, err);
     }
@@ -303,10 +319,12 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     delete p;
     return set_error(IFGF_EINVAL, "IFGF_DERIV_FD needs the matrix-core orders (Pa = 5 or 6, 3 <= Ps <= 6)");
   }
-  if (p->mfma)
+  if (p->mfma && !opt.keep_pair_tables)
     for (int d = 1; d <= H.D; ++d) std::vector<int32_t>().swap(H.lev[d].pp_slot);
   p->groups.assign(H.D + 1, PropGroups());
   p->ttiles.assign(H.D + 1, TargetTiles());
+  p->tc_tile.assign(H.D + 1, std::vector<int64_t>());
+  p->tc_i0.assign(H.D + 1, std::vector<int64_t>());
   int64_t max_pairs = 0;
   p->lev.assign(H.D + 1, DevLevel());
   for (int d = 1; d <= H.D; ++d) {
@@ -371,23 +389,30 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
       TT.cnt = cn;
       TT.tgt = tg;
       TT.e = ee;
-      max_pairs = std::max(max_pairs, L.tp_off.back());
+      p->tc_tile[d] = L.tc_tile;
+      p->tc_i0[d] = L.tc_i0;
+      max_pairs = std::max(max_pairs, L.tc_max_pairs);
     }
     std::vector<int32_t>().swap(L.tt_slot);
     std::vector<int64_t>().swap(L.tt_start);
     std::vector<uint8_t>().swap(L.tt_cnt);
     std::vector<int32_t>().swap(L.ts_tgt);
     std::vector<int32_t>().swap(L.ts_e);
-    if (d >= 3) p->max_slots = std::max(p->max_slots, L.nslots);
+    if (d >= 3) {
+      p->max_slots = std::max(p->max_slots, L.nslots);
+      p->par_slots[(H.D - d) & 1] = std::max(p->par_slots[(H.D - d) & 1], L.nslots);
+    }
     // the host copies of the large pair tables are no longer needed
-    std::vector<int32_t>().swap(L.tp_slot);
-    std::vector<int32_t>().swap(L.pp_slot);
+    if (!opt.keep_pair_tables) {
+      std::vector<int32_t>().swap(L.tp_slot);
+      std::vector<int32_t>().swap(L.pp_slot);
+    }
   }
   if (opt.deriv_mode == IFGF_DERIV_FD)
     for (int d = 3; d <= H.D; ++d)
       if (H.lev[d].tp_off.back() > 0 && p->ttiles[d].ntiles == 0) {
         delete p;
-        return set_error(IFGF_EINVAL, "IFGF_DERIV_FD needs the target tiles of every level (fewer than 2^31 pairs)");
+        return set_error(IFGF_EINVAL, "IFGF_DERIV_FD needs the target tiles of every level");
       }
   // right-hand sides stacked into the cone-data columns (matrix-core path)
   p->rcap = p->mfma ? std::min(std::min(opt.max_nrhs, opt.batch_columns), max_batch_columns(p->fp32, opt.Ps, opt.Pa))
@@ -417,17 +442,21 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     }
   }
   if (max_pairs > 0) {
-    p->d_res = ar.alloc((size_t)p->elem * 56 * (size_t)max_pairs);
+    p->res_bytes = (size_t)p->elem * 56 * (size_t)max_pairs;
+    p->d_res = ar.alloc(p->res_bytes);
     if (!p->d_res) {
       delete p;
       return set_error(IFGF_ENOMEM, "device workspace allocation failed");
     }
   }
   if (p->max_slots > 0) {
-    size_t vb = p->mfma ? (size_t)p->elem * (size_t)p->max_slots * kslot_rows(opt.Ps, opt.Pa) * 32 * p->rcap
-                        : sizeof(double2) * (size_t)p->max_slots * p->ic.npts * kCols;
-    p->d_vals[0] = static_cast<double2*>(ar.alloc(vb));
-    p->d_vals[1] = static_cast<double2*>(ar.alloc(vb));
+    for (int b = 0; b < 2; ++b) {
+      const size_t slots = (size_t)std::max<int64_t>(p->par_slots[b], 1);
+      const size_t vb = p->mfma ? (size_t)p->elem * slots * kslot_rows(opt.Ps, opt.Pa) * 32 * p->rcap
+                                : sizeof(double2) * slots * p->ic.npts * kCols;
+      p->d_vals[b] = static_cast<double2*>(ar.alloc(vb));
+      p->vals_bytes += vb;
+    }
     if (!p->d_vals[0] || !p->d_vals[1]) {
       delete p;
       return set_error(IFGF_ENOMEM, "device cone-grid allocation failed");
@@ -480,12 +509,23 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
       for (int d = H.D; d >= 3; --d) {
         ev = T.begin(st);
         if (R == 1 && p->d_res && p->ttiles[d].ntiles > 0) {
-          // cone-major tiles on the matrix cores, then the per-target sums
-          if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, p->lev[d], p->ic, p->ttiles[d], p->d_xs, p->d_nrm, k0, k1,
-                                    p->d_vals[cur], p->d_res, p->opt.deriv_mode == IFGF_DERIV_FD, st)) !=
-                  hipSuccess ||
-              (e = mf_targets_reduce(p->fp32, p->lev[d], n, p->d_res, p->d_out_s, st)) != hipSuccess)
-            return set_hip_error(e, "targets");
+          // cone-major tiles on the matrix cores, then the per-target sums,
+          // one chunk of consecutive targets at a time (bounded result buffer)
+          const std::vector<int64_t>& ct = p->tc_tile[d];
+          const std::vector<int64_t>& ci = p->tc_i0[d];
+          for (size_t c = 0; c + 1 < ct.size(); ++c) {
+            TargetTiles sub = p->ttiles[d];
+            sub.slot += ct[c];
+            sub.start += ct[c];
+            sub.cnt += ct[c];
+            sub.ntiles = ct[c + 1] - ct[c];
+            if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, p->lev[d], p->ic, sub, p->d_xs, p->d_nrm, k0, k1,
+                                      p->d_vals[cur], p->d_res, p->opt.deriv_mode == IFGF_DERIV_FD, st)) !=
+                    hipSuccess ||
+                (e = mf_targets_reduce(p->fp32, p->lev[d], ci[c], ci[c + 1], p->d_res, p->d_out_s, st)) !=
+                    hipSuccess)
+              return set_hip_error(e, "targets");
+          }
         } else if ((e = mf_targets(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1,
                                    p->d_vals[cur], p->d_out_s, st)) != hipSuccess) {
           return set_hip_error(e, "targets");
@@ -616,7 +656,9 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
                   ",\"near_pairs\":" + std::to_string(H.near_pairs) +
                   ",\"leaf_pairs\":" + std::to_string(H.leaf_pairs) +
                   ",\"device_bytes\":" + std::to_string(p->arena.bytes()) +
-                  ",\"workspace_elem_bytes\":" + std::to_string(p->elem) + ",\"levels\":[";
+                  ",\"workspace_elem_bytes\":" + std::to_string(p->elem) +
+                  ",\"cone_buffer_bytes\":" + std::to_string(p->vals_bytes) +
+                  ",\"target_result_bytes\":" + std::to_string(p->res_bytes) + ",\"levels\":[";
   for (int d = 3; d <= H.D; ++d) {
     const HostLevel& L = H.lev[d];
     s += std::string(d > 3 ? "," : "") + "{\"d\":" + std::to_string(d) + ",\"boxes\":" +
@@ -712,6 +754,13 @@ int ifgf_set_precision(ifgf_plan_t p, int precision, int* previous) {
   p->fp32 = precision == IFGF_FP32;
   p->opt.precision = precision;
   return IFGF_OK;
+}
+
+int ifgf_precisions(ifgf_plan_t p) {
+  if (!p || p->opt.host_only) return 0;
+  int m = p->elem >= 8 ? 1 : 0;
+  if (p->mfma && p->opt.deriv_mode != IFGF_DERIV_FD) m |= 2;
+  return m;
 }
 
 int ifgf_check(ifgf_plan_t p, void* stream, unsigned* flags) {

@@ -426,6 +426,7 @@ class Fgmres {
     inf_.seconds = std::chrono::duration<double>(t1 - t0_).count();
     inf_.precond_iters = pc_iters_;
     inf_.fallbacks = fallbacks_;
+    inf_.residual_fp64 = fp64_res_ ? 1 : 0;
     *done = true;
     return 0;
   }
@@ -541,6 +542,8 @@ extern "C" int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, i
   int rc = solver_size(nm, &n);
   if (rc) return rc;
   const bool precond = nmuller_precond(nm) != nullptr;
+  // true residuals on the FP64 form when the plan holds its buffers
+  const bool res64 = (ifgf_precisions(nmuller_ifgf(nm)) & 1) != 0;
   const int64_t m = 4 * n;
   const int basis = (restart > 0 && restart < maxit) ? restart : maxit;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -568,7 +571,7 @@ extern "C" int nmuller_solve(nmuller_t nm, const void* rhs, int nrhs, void* y, i
       const double2* b = static_cast<const double2*>(rhs) + (int64_t)(r0 + i) * m;
       double2* x = static_cast<double2*>(y) + (int64_t)(r0 + i) * m;
       if (!use_x0) hipLaunchKernelGGL(k_fill, dim3(nblk(m)), dim3(kBS), 0, st, x, m);
-      Gs[i] = std::make_unique<Fgmres>(*Ss[i], b, x, rtol, maxit, precond, nullptr, true);
+      Gs[i] = std::make_unique<Fgmres>(*Ss[i], b, x, rtol, maxit, precond, nullptr, res64);
     }
     if (gn == 1) {
       if ((rc = run_one(*Gs[0], nm, m, st))) return rc;
@@ -636,7 +639,8 @@ extern "C" int nmuller_solve_noalloc(nmuller_t nm, const void* rhs, void* y, int
   if ((rc = S.init_in(base, kScratchBytes, basis, precond))) return rc;
   double2* x = static_cast<double2*>(y);
   if (!use_x0) hipLaunchKernelGGL(k_fill, dim3(nblk(S.m)), dim3(kBS), 0, S.st, x, S.m);
-  Fgmres G(S, static_cast<const double2*>(rhs), x, rtol, maxit, precond, nullptr, true);
+  Fgmres G(S, static_cast<const double2*>(rhs), x, rtol, maxit, precond, nullptr,
+           (ifgf_precisions(nmuller_ifgf(nm)) & 1) != 0);
   if ((rc = run_one(G, nm, S.m, S.st))) return rc;
   if (info) *info = G.info();
   if ((rc = ifgf_check(nmuller_ifgf(nm), stream, nullptr))) return rc;

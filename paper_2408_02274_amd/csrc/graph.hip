@@ -1,11 +1,15 @@
 // Batching by graph capture: the N-Mueller applies of several operators
-// (bodies) and right-hand sides recorded once into one hipGraph and replayed
-// with a single launch (project addition; the paper runs one forward map at
-// a time).  Nothing in the apply path allocates, copies between host and
-// device or synchronises, so the captured work is exactly the eager work.
+// (bodies, or copies of one operator holding different right-hand sides)
+// recorded once into one hipGraph and replayed with a single launch (project
+// addition; the paper runs one forward map at a time).  Each operator's
+// applies form one branch of the graph, so small bodies that leave most of
+// the GPU idle run side by side.  Nothing in the apply path allocates, copies
+// between host and device or synchronises, so the captured work is exactly
+// the eager work.
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/ifgf.h"
 #include "device.hpp"
@@ -17,6 +21,7 @@ struct ifgf_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t nodes = 0;
+  int branches = 0;
   ~ifgf_graph_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -36,24 +41,56 @@ int nmuller_graph_capture(ifgf_graph_t* out, int nops, const nmuller_t* ops, con
     if (timing_on(nmuller_ifgf(ops[i])))
       return set_error(IFGF_EINVAL, "switch per-kernel timing off before capturing");
   }
+  // One branch per distinct operator: applies of one operator share its
+  // workspaces and stay in order on their branch; different operators share
+  // nothing and run side by side.  The branches fork from and join into the
+  // capture stream.
+  std::vector<nmuller_t> distinct;
+  std::vector<int> branch(nops);
+  for (int i = 0; i < nops; ++i) {
+    int b = 0;
+    while (b < (int)distinct.size() && distinct[b] != ops[i]) ++b;
+    if (b == (int)distinct.size()) distinct.push_back(ops[i]);
+    branch[i] = b;
+  }
+  const int nb = (int)distinct.size();
   ifgf_graph_s* g = new (std::nothrow) ifgf_graph_s();
   if (!g) return set_error(IFGF_ENOMEM, "host allocation failed");
+  std::vector<hipStream_t> bs(nb, nullptr);
+  std::vector<hipEvent_t> ev(nb + 1, nullptr);
   hipStream_t cs = nullptr;
+  auto cleanup = [&]() {
+    for (hipStream_t s2 : bs)
+      if (s2) (void)hipStreamDestroy(s2);
+    for (hipEvent_t e2 : ev)
+      if (e2) (void)hipEventDestroy(e2);
+    if (cs) (void)hipStreamDestroy(cs);
+  };
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  for (int b = 0; b < nb && e == hipSuccess; ++b) e = hipStreamCreateWithFlags(&bs[b], hipStreamNonBlocking);
+  for (int b = 0; b <= nb && e == hipSuccess; ++b) e = hipEventCreateWithFlags(&ev[b], hipEventDisableTiming);
   if (e != hipSuccess) {
+    cleanup();
     delete g;
-    return set_hip_error(e, "capture stream");
+    return set_hip_error(e, "capture streams");
   }
   if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
-    (void)hipStreamDestroy(cs);
+    cleanup();
     delete g;
     return set_hip_error(e, "hipStreamBeginCapture");
   }
   int rc = IFGF_OK;
-  for (int i = 0; i < nops && rc == IFGF_OK; ++i) rc = nmuller_apply(ops[i], y[i], nrhs[i], Ay[i], cs);
+  if ((e = hipEventRecord(ev[nb], cs)) != hipSuccess) rc = set_hip_error(e, "fork event");
+  for (int b = 0; b < nb && rc == IFGF_OK; ++b)
+    if ((e = hipStreamWaitEvent(bs[b], ev[nb], 0)) != hipSuccess) rc = set_hip_error(e, "fork");
+  for (int i = 0; i < nops && rc == IFGF_OK; ++i) rc = nmuller_apply(ops[i], y[i], nrhs[i], Ay[i], bs[branch[i]]);
+  for (int b = 0; b < nb && rc == IFGF_OK; ++b) {
+    if ((e = hipEventRecord(ev[b], bs[b])) != hipSuccess || (e = hipStreamWaitEvent(cs, ev[b], 0)) != hipSuccess)
+      rc = set_hip_error(e, "join");
+  }
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(cs, &graph);
-  (void)hipStreamDestroy(cs);
+  cleanup();
   g->graph = graph;
   if (rc != IFGF_OK) {
     delete g;
@@ -66,6 +103,7 @@ int nmuller_graph_capture(ifgf_graph_t* out, int nops, const nmuller_t* ops, con
   size_t nn = 0;
   (void)hipGraphGetNodes(graph, nullptr, &nn);
   g->nodes = (int64_t)nn;
+  g->branches = nb;
   if ((e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
     delete g;
     return set_hip_error(e, "hipGraphInstantiate");

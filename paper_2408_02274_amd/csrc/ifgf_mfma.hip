@@ -1000,21 +1000,24 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   }
 }
 
-// out_s[i][k] += sum over the target pairs e of i of res[e][k], k < 28 (FP64 sums)
+// out_s[i][k] += sum over the target pairs e of i of res[e - e0][k], k < 28,
+// for targets i0 <= i < i1 whose pairs start at e0 = tp_off[i0] (FP64 sums)
 template <class T>
-__global__ void __launch_bounds__(256) k_targets_reduce(const int64_t* __restrict__ tp_off, int64_t n,
+__global__ void __launch_bounds__(256) k_targets_reduce(const int64_t* __restrict__ tp_off, int64_t i0, int64_t i1,
                                                         const T* __restrict__ res, double2* __restrict__ out_s) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n * 28) return;
-  const int64_t i = g / 28;
+  if (g >= (i1 - i0) * 28) return;
+  const int64_t i = i0 + g / 28;
   const int k = (int)(g % 28);
+  const int64_t e0 = tp_off[i0];
   double re = 0.0, im = 0.0;
-  for (int64_t e = tp_off[i]; e < tp_off[i + 1]; ++e) {
+  for (int64_t e = tp_off[i] - e0; e < tp_off[i + 1] - e0; ++e) {
     re += (double)res[e * 56 + 2 * k];
     im += (double)res[e * 56 + 2 * k + 1];
   }
-  const double2 v = out_s[g];
-  out_s[g] = make_double2(v.x + re, v.y + im);
+  const int64_t o = i * 28 + k;
+  const double2 v = out_s[o];
+  out_s[o] = make_double2(v.x + re, v.y + im);
 }
 
 inline unsigned nblk(int64_t w, int bs) { return (unsigned)((w + bs - 1) / bs); }
@@ -1195,15 +1198,15 @@ hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const 
               : dispatch_targets_tiles<double>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
 }
 
-hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,
+hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t i0, int64_t i1, const void* res, double2* out_s,
                              hipStream_t st) {
-  if (n <= 0) return hipSuccess;
+  if (i1 <= i0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_targets_reduce<float>, dim3(nblk(n * 28, 256)), dim3(256), 0, st, L.tp_off, n,
-                       static_cast<const float*>(res), out_s);
+    hipLaunchKernelGGL(k_targets_reduce<float>, dim3(nblk((i1 - i0) * 28, 256)), dim3(256), 0, st, L.tp_off, i0,
+                       i1, static_cast<const float*>(res), out_s);
   else
-    hipLaunchKernelGGL(k_targets_reduce<double>, dim3(nblk(n * 28, 256)), dim3(256), 0, st, L.tp_off, n,
-                       static_cast<const double*>(res), out_s);
+    hipLaunchKernelGGL(k_targets_reduce<double>, dim3(nblk((i1 - i0) * 28, 256)), dim3(256), 0, st, L.tp_off, i0,
+                       i1, static_cast<const double*>(res), out_s);
   return hipGetLastError();
 }
 

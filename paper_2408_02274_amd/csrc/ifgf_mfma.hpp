@@ -59,7 +59,9 @@ hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const
 hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
                             const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
                             bool fd, hipStream_t st);
-hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t n, const void* res, double2* out_s,
+// out_s[i] += the per-pair results of targets i in [i0, i1), whose pairs
+// start at tp_off[i0] in res
+hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t i0, int64_t i1, const void* res, double2* out_s,
                              hipStream_t st);
 
 }  // namespace ifgf

@@ -6,6 +6,7 @@
 // derivatives via Chebyshev recurrences); Sec. III-H (local corrections).
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <memory>
 
 #include <cmath>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "../../include/ifgf.h"
+#include "corrections.hpp"
 #include "device.hpp"
 #include "nmuller_host.hpp"
 #include "precond.hpp"
@@ -268,6 +270,8 @@ struct nmuller_s {
   int64_t* d_row_off = nullptr;
   int32_t* d_pair_patch = nullptr;
   double2* d_vals = nullptr;
+  int cor_on_device = 0;      // corrections built by the device builder
+  double cor_seconds = 0.0;   // wall time of the correction build
   double2* d_phi = nullptr;   // [max_nrhs][8][n]
   double2* d_sd = nullptr;    // [max_nrhs][2][14][n]
   Mat mat{};
@@ -305,6 +309,7 @@ void nmuller_default_params(nmuller_params* p) {
   p->delta_factor = 1.0;
   p->nbeta = 0;
   p->d_cov = 4;
+  p->corrections_on_host = 0;
 }
 
 int nmuller_plan(nmuller_t* out, const nmuller_params* prm, const double* points,
@@ -344,15 +349,31 @@ int nmuller_plan(nmuller_t* out, const nmuller_params* prm, const double* points
   if (prm->delta_factor > 0) sp.delta_factor = prm->delta_factor;
   sp.nbeta = prm->nbeta;
   if (prm->d_cov >= 2) sp.d = prm->d_cov;
-  try {
-    if (build_corrections(nm->geo, ki, ke, sp, nm->cor, err)) {
+  const bool on_device = !nm->host_only && !prm->corrections_on_host &&
+                         device_corrections_supported(prm->Nc, prm->nbeta);
+  const auto t_cor = std::chrono::steady_clock::now();
+  if (on_device) {
+    DevCorrections dc;
+    if ((rc = build_corrections_device(nm->geo, ki, ke, sp, nm->arena, dc, nm->cor, err))) {
       delete nm;
-      return set_error(IFGF_EINVAL, err);
+      return set_error(rc, err);
     }
-  } catch (const std::bad_alloc&) {
-    delete nm;
-    return set_error(IFGF_ENOMEM, "host allocation failed in the singular quadrature");
+    nm->d_row_off = dc.row_off;
+    nm->d_pair_patch = dc.pair_patch;
+    nm->d_vals = dc.vals;
+    nm->cor_on_device = 1;
+  } else {
+    try {
+      if (build_corrections(nm->geo, ki, ke, sp, nm->cor, err)) {
+        delete nm;
+        return set_error(IFGF_EINVAL, err);
+      }
+    } catch (const std::bad_alloc&) {
+      delete nm;
+      return set_error(IFGF_ENOMEM, "host allocation failed in the singular quadrature");
+    }
   }
+  nm->cor_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_cor).count();
   if (nm->host_only) {
     *out = nm;
     return IFGF_OK;
@@ -368,18 +389,20 @@ int nmuller_plan(nmuller_t* out, const nmuller_params* prm, const double* points
     delete nm;
     return rc;
   }
-  const int64_t* ro = nullptr;
-  const int32_t* pp = nullptr;
-  const double* vv = nullptr;
-  if ((rc = up(ar, nm->cor.row_off, &ro)) || (rc = up(ar, nm->cor.pair_patch, &pp)) ||
-      (rc = up(ar, nm->cor.vals, &vv))) {
-    delete nm;
-    return rc;
+  if (!on_device) {
+    const int64_t* ro = nullptr;
+    const int32_t* pp = nullptr;
+    const double* vv = nullptr;
+    if ((rc = up(ar, nm->cor.row_off, &ro)) || (rc = up(ar, nm->cor.pair_patch, &pp)) ||
+        (rc = up(ar, nm->cor.vals, &vv))) {
+      delete nm;
+      return rc;
+    }
+    nm->d_row_off = const_cast<int64_t*>(ro);
+    nm->d_pair_patch = const_cast<int32_t*>(pp);
+    nm->d_vals = reinterpret_cast<double2*>(const_cast<double*>(vv));
+    std::vector<double>().swap(nm->cor.vals);   // device copy is the working one
   }
-  nm->d_row_off = const_cast<int64_t*>(ro);
-  nm->d_pair_patch = const_cast<int32_t*>(pp);
-  nm->d_vals = reinterpret_cast<double2*>(const_cast<double*>(vv));
-  std::vector<double>().swap(nm->cor.vals);   // device copy is the working one
   nm->d_phi = static_cast<double2*>(ar.alloc(sizeof(double2) * (size_t)nm->max_nrhs * 8 * n));
   nm->d_sd = static_cast<double2*>(ar.alloc(sizeof(double2) * (size_t)nm->max_nrhs * 28 * n));
   if (!nm->d_phi || !nm->d_sd) {
@@ -461,9 +484,28 @@ int nmuller_corrections(nmuller_t nm, int64_t* npairs, int64_t* row_off, int32_t
   if (pair_patch)
     std::memcpy(pair_patch, nm->cor.pair_patch.data(), nm->cor.pair_patch.size() * sizeof(int32_t));
   if (vals) {
-    if (nm->cor.vals.empty()) return set_error(IFGF_ENOTPLANNED, "values are kept only by host_only plans");
-    std::memcpy(vals, nm->cor.vals.data(), nm->cor.vals.size() * sizeof(double));
+    if (!nm->cor.vals.empty()) {
+      std::memcpy(vals, nm->cor.vals.data(), nm->cor.vals.size() * sizeof(double));
+    } else if (nm->d_vals) {
+      const size_t nq = (size_t)nm->gd.nc * nm->gd.nc;
+      hipError_t e = hipMemcpy(vals, nm->d_vals, sizeof(double2) * 4 * nq * (size_t)*npairs, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return set_hip_error(e, "hipMemcpy");
+    } else {
+      return set_error(IFGF_ENOTPLANNED, "no correction values");
+    }
   }
+  return IFGF_OK;
+}
+
+int nmuller_plan_info(nmuller_t nm, double* info, int cap) {
+  clear_error();
+  if (!nm || !info) return set_error(IFGF_EINVAL, "null argument");
+  if (cap < 4) return set_error(IFGF_EINVAL, "info needs 4 entries");
+  const double npairs = nm->cor.row_off.empty() ? 0.0 : (double)nm->cor.row_off.back();
+  info[0] = nm->cor_on_device;
+  info[1] = nm->cor_seconds;
+  info[2] = npairs;
+  info[3] = npairs * 4.0 * nm->geo.nc * nm->geo.nc * 16.0;
   return IFGF_OK;
 }
 

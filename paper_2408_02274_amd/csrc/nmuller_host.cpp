@@ -61,6 +61,14 @@ void transform_matrix(int n, std::vector<double>& M) {
   }
 }
 
+// x^d for a small integer d >= 1 by repeated multiplication (the device
+// builder forms the same products in the same order)
+inline double ipow(double x, int d) {
+  double p = x;
+  for (int k = 1; k < d; ++k) p = p * x;
+  return p;
+}
+
 // Kress map (eq. mk_cov_1, mk_cov_2) and its derivative
 inline double knu(double t, int d) {
   double a = (kPi - t) / kPi;
@@ -71,14 +79,14 @@ inline double kdnu(double t, int d) {
   return -(3.0 / kPi) * (1.0 / d - 0.5) * a * a + 1.0 / (d * kPi);
 }
 inline double kw(double t, int d) {
-  double a = std::pow(knu(t, d), d), b = std::pow(knu(2 * kPi - t, d), d);
+  double a = ipow(knu(t, d), d), b = ipow(knu(2 * kPi - t, d), d);
   return 2 * kPi * a / (a + b);
 }
 inline double kdw(double t, int d) {
   double n1 = knu(t, d), n2 = knu(2 * kPi - t, d);
-  double a = std::pow(n1, d), b = std::pow(n2, d);
-  double da = d * std::pow(n1, d - 1) * kdnu(t, d);
-  double db = -d * std::pow(n2, d - 1) * kdnu(2 * kPi - t, d);
+  double a = ipow(n1, d), b = ipow(n2, d);
+  double da = d * ipow(n1, d - 1) * kdnu(t, d);
+  double db = -d * ipow(n2, d - 1) * kdnu(2 * kPi - t, d);
   return 2 * kPi * (da * b - a * db) / ((a + b) * (a + b));
 }
 
@@ -232,25 +240,29 @@ int build_surface(SurfaceGeo& g, int P, int nc, const double* x, const double* d
   return 0;
 }
 
-int build_corrections(const SurfaceGeo& g, double k_int, double k_ext, const SingParams& sp,
-                      Corrections& cor, std::string& err) {
+int sing_tables(const SurfaceGeo& g, const SingParams& sp, SingTables& t, std::string& err) {
   const int nc = g.nc, P = g.P;
   const int nq = nc * nc;
-  const int64_t n = g.n;
-  const int nb = sp.nbeta > 0 ? sp.nbeta : 6 * nc;
-  const int d = sp.d;
-  if (nb > 128) {
+  t.nb = sp.nbeta > 0 ? sp.nbeta : 6 * nc;
+  if (t.nb > 128) {
     err = "nbeta must be <= 128";
     return -1;
   }
-  std::vector<double> M;
-  transform_matrix(nc, M);
-  std::vector<double> tn(nc), tb(nb), wb(nb);
-  cheb_nodes(nc, tn.data());
-  cheb_nodes(nb, tb.data());
-  fejer(nb, wb.data());
+  transform_matrix(nc, t.M);
+  t.tn.resize(nc);
+  t.tb.resize(t.nb);
+  t.wb.resize(t.nb);
+  cheb_nodes(nc, t.tn.data());
+  cheb_nodes(t.nb, t.tb.data());
+  fejer(t.nb, t.wb.data());
+  t.gold = kGold;
   // per patch: Chebyshev coefficients of the node coordinates, bounding box, delta
-  std::vector<double> A((size_t)P * nq * 3), lo(3 * P), hi(3 * P), delta(P);
+  t.A.assign((size_t)P * nq * 3, 0.0);
+  t.lo.resize(3 * (size_t)P);
+  t.hi.resize(3 * (size_t)P);
+  t.delta.resize(P);
+  const std::vector<double>& M = t.M;
+#pragma omp parallel for schedule(static)
   for (int p = 0; p < P; ++p) {
     const double* xp = &g.x[(size_t)3 * p * nq];
     std::vector<double> tmp((size_t)nq * 3, 0.0);
@@ -258,7 +270,7 @@ int build_corrections(const SurfaceGeo& g, double k_int, double k_ext, const Sin
       for (int j = 0; j < nc; ++j)
         for (int i = 0; i < nc; ++i)
           for (int c = 0; c < 3; ++c) tmp[3 * (m * nc + j) + c] += M[m * nc + i] * xp[3 * (i * nc + j) + c];
-    double* Ap = &A[(size_t)3 * p * nq];
+    double* Ap = &t.A[(size_t)3 * p * nq];
     for (int m = 0; m < nc; ++m)
       for (int nn = 0; nn < nc; ++nn) {
         double s[3] = {0, 0, 0};
@@ -266,16 +278,38 @@ int build_corrections(const SurfaceGeo& g, double k_int, double k_ext, const Sin
           for (int c = 0; c < 3; ++c) s[c] += M[nn * nc + j] * tmp[3 * (m * nc + j) + c];
         for (int c = 0; c < 3; ++c) Ap[3 * (m * nc + nn) + c] = s[c];
       }
+    double* lo = &t.lo[3 * (size_t)p];
+    double* hi = &t.hi[3 * (size_t)p];
     for (int c = 0; c < 3; ++c) {
-      lo[3 * p + c] = hi[3 * p + c] = xp[c];
+      lo[c] = hi[c] = xp[c];
       for (int q = 0; q < nq; ++q) {
-        lo[3 * p + c] = std::min(lo[3 * p + c], xp[3 * q + c]);
-        hi[3 * p + c] = std::max(hi[3 * p + c], xp[3 * q + c]);
+        lo[c] = std::min(lo[c], xp[3 * q + c]);
+        hi[c] = std::max(hi[c], xp[3 * q + c]);
       }
     }
-    double e0 = hi[3 * p] - lo[3 * p], e1 = hi[3 * p + 1] - lo[3 * p + 1], e2 = hi[3 * p + 2] - lo[3 * p + 2];
-    delta[p] = sp.delta_factor * std::sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    double e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
+    t.delta[p] = sp.delta_factor * std::sqrt(e0 * e0 + e1 * e1 + e2 * e2);
   }
+  return 0;
+}
+
+int build_corrections(const SurfaceGeo& g, double k_int, double k_ext, const SingParams& sp,
+                      Corrections& cor, std::string& err) {
+  const int nc = g.nc, P = g.P;
+  const int nq = nc * nc;
+  const int64_t n = g.n;
+  const int d = sp.d;
+  SingTables t;
+  if (sing_tables(g, sp, t, err)) return -1;
+  const int nb = t.nb;
+  const std::vector<double>& M = t.M;
+  const std::vector<double>& tn = t.tn;
+  const std::vector<double>& tb = t.tb;
+  const std::vector<double>& wb = t.wb;
+  const std::vector<double>& A = t.A;
+  const std::vector<double>& lo = t.lo;
+  const std::vector<double>& hi = t.hi;
+  const std::vector<double>& delta = t.delta;
 
   // pass 1: singular pairs with their closest points
   std::vector<std::vector<int32_t>> rp(n);

@@ -43,8 +43,21 @@ struct Corrections {
   std::vector<double> vals;         // [npairs][4][nc*nc][2]
 };
 
+// Inputs of the singular quadrature shared by the host and device builders:
+// Chebyshev coefficients of each patch's node coordinates A [P][Nc^2][3]
+// (coefficient (m, n) of eta_p), the patch node bounding boxes lo, hi [P][3]
+// and radii delta [P] of eq. patch_sing, the Chebyshev nodes tn [Nc] of the
+// patches, the Fejer rule (tb, wb) [nb] of eq. int_moments_cov, the
+// values -> coefficients matrix M [Nc][Nc] and the golden-section ratio.
+struct SingTables {
+  int nb = 0;
+  double gold = 0.0;
+  std::vector<double> A, lo, hi, delta, tn, tb, wb, M;
+};
+
 int build_surface(SurfaceGeo& g, int P, int nc, const double* x, const double* du,
                   const double* dv, std::string& err);
+int sing_tables(const SurfaceGeo& g, const SingParams& sp, SingTables& t, std::string& err);
 int build_corrections(const SurfaceGeo& g, double k_int, double k_ext, const SingParams& sp,
                       Corrections& c, std::string& err);
 

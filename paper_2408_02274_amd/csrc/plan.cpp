@@ -97,30 +97,50 @@ static int find_slot(const HostLevel& L, int64_t box, int cone) {
   return (int)(L.slot_off[box] + (it - b));
 }
 
-void build_target_tiles(HostLevel& L, int64_t n) {
+void build_target_tiles(HostLevel& L, int64_t n, int64_t chunk_pairs) {
   const int64_t np = L.tp_off.empty() ? 0 : L.tp_off[n];
-  if (np <= 0 || np >= ((int64_t)1 << 31) || L.nslots <= 0) return;
-  std::vector<int64_t> off(L.nslots + 1, 0);
-  for (int64_t e = 0; e < np; ++e) off[L.tp_slot[e] + 1] += 1;
-  for (int64_t s = 0; s < L.nslots; ++s) off[s + 1] += off[s];
-  std::vector<int64_t> cur(off.begin(), off.end() - 1);
-  L.ts_tgt.resize(np);
-  L.ts_e.resize(np);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t e = L.tp_off[i]; e < L.tp_off[i + 1]; ++e) {
-      const int64_t pos = cur[L.tp_slot[e]]++;
-      L.ts_tgt[pos] = (int32_t)i;
-      L.ts_e[pos] = (int32_t)e;
-    }
   L.tt_slot.clear();
   L.tt_start.clear();
   L.tt_cnt.clear();
-  for (int64_t s = 0; s < L.nslots; ++s)
-    for (int64_t k = off[s]; k < off[s + 1]; k += 8) {
-      L.tt_slot.push_back((int32_t)s);
-      L.tt_start.push_back(k);
-      L.tt_cnt.push_back((uint8_t)std::min<int64_t>(8, off[s + 1] - k));
-    }
+  L.tc_tile.assign(1, 0);
+  L.tc_i0.assign(1, 0);
+  L.tc_max_pairs = 0;
+  if (np <= 0 || L.nslots <= 0) {
+    L.ts_tgt.clear();
+    L.ts_e.clear();
+    L.tc_i0.push_back(n);
+    L.tc_tile.push_back(0);
+    return;
+  }
+  L.ts_tgt.resize(np);
+  L.ts_e.resize(np);
+  std::vector<int64_t> off(L.nslots + 1, 0);
+  for (int64_t i0 = 0; i0 < n;) {
+    const int64_t e0 = L.tp_off[i0];
+    int64_t i1 = i0 + 1;
+    while (i1 < n && L.tp_off[i1 + 1] - e0 <= chunk_pairs) ++i1;
+    const int64_t e1 = L.tp_off[i1];
+    L.tc_max_pairs = std::max(L.tc_max_pairs, e1 - e0);
+    std::fill(off.begin(), off.end(), 0);
+    for (int64_t e = e0; e < e1; ++e) off[L.tp_slot[e] + 1] += 1;
+    for (int64_t s = 0; s < L.nslots; ++s) off[s + 1] += off[s];
+    std::vector<int64_t> cur(off.begin(), off.end() - 1);
+    for (int64_t i = i0; i < i1; ++i)
+      for (int64_t e = L.tp_off[i]; e < L.tp_off[i + 1]; ++e) {
+        const int64_t pos = e0 + cur[L.tp_slot[e]]++;
+        L.ts_tgt[pos] = (int32_t)i;
+        L.ts_e[pos] = (int32_t)(e - e0);
+      }
+    for (int64_t s = 0; s < L.nslots; ++s)
+      for (int64_t k = off[s]; k < off[s + 1]; k += 8) {
+        L.tt_slot.push_back((int32_t)s);
+        L.tt_start.push_back(e0 + k);
+        L.tt_cnt.push_back((uint8_t)std::min<int64_t>(8, off[s + 1] - k));
+      }
+    L.tc_tile.push_back((int64_t)L.tt_slot.size());
+    L.tc_i0.push_back(i1);
+    i0 = i1;
+  }
 }
 
 void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts) {
@@ -447,7 +467,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
       }
     }
     if (bad) { err = "internal: cousin target outside relevant cones"; return -1; }
-    build_target_tiles(L, n);
+    build_target_tiles(L, n, pp.target_chunk_pairs > 0 ? pp.target_chunk_pairs : kTargetChunkPairs);
     progress("relevant cones and target pairs", d, L.nslots);
     // propagation pairs into level d-1
     if (d >= 4) {

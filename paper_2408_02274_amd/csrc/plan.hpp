@@ -55,14 +55,19 @@ struct HostLevel {
   // index of the tile's first point in pg_pts, child cone index (a cone index
   // needs up to 31 bits: 2^30 cones per box at level 3 of a 40-wavelength body)
   std::vector<int32_t> pt_rec;
-  // the target pairs grouped by cone slot (targets ascending within a slot),
-  // cut into tiles of at most 8 targets: tile t covers entries
-  // [tt_start[t], tt_start[t] + tt_cnt[t]) of ts_tgt (sorted target) and
-  // ts_e (its index in the target-major pair list), all of slot tt_slot[t]
+  // the target pairs in chunks of consecutive targets (chunk c: targets
+  // [tc_i0[c], tc_i0[c+1]), pairs from tp_off[tc_i0[c]], at most
+  // tc_max_pairs of them), within a chunk grouped by cone slot (targets
+  // ascending within a slot) and cut into tiles of at most 8 targets: tile t
+  // covers entries [tt_start[t], tt_start[t] + tt_cnt[t]) of ts_tgt (sorted
+  // target) and ts_e (its pair index relative to the chunk's first pair), all
+  // of slot tt_slot[t]; the tiles of chunk c are [tc_tile[c], tc_tile[c+1])
   std::vector<int32_t> ts_tgt, ts_e;
   std::vector<int32_t> tt_slot;
   std::vector<int64_t> tt_start;
   std::vector<uint8_t> tt_cnt;
+  std::vector<int64_t> tc_tile, tc_i0;
+  int64_t tc_max_pairs = 0;
 };
 
 struct HostPlan {
@@ -80,10 +85,14 @@ struct HostPlan {
   int64_t near_pairs = 0, leaf_pairs = 0;
 };
 
+// Pairs per chunk of the per-pair target results: 1 GiB of FP64 results.
+constexpr int64_t kTargetChunkPairs = ((int64_t)1 << 30) / (56 * 8);
+
 struct PlanParams {
   int Ps = 3, Pa = 5, ns_init = 1, na_init = 2, refine_radial = 1;
   double leaf_wavelengths = 0.25;
   int verbose = 0;   // progress lines on stderr
+  int64_t target_chunk_pairs = 0;   // target pairs per result chunk (0: kTargetChunkPairs)
 };
 
 // Returns 0 on success, else fills err.
@@ -91,9 +100,18 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
                     const double* w, double k0, double k1, const PlanParams& pp,
                     std::string& err);
 
-// Group the target pairs of level L by cone slot and cut them into tiles of
-// at most 8 targets (requires fewer than 2^31 pairs; else leaves them empty).
-void build_target_tiles(HostLevel& L, int64_t n);
+// The same tables built by kernels on the current device (host arrays in,
+// HostPlan filled on the host; device temporaries freed on return).  Returns
+// 0 on success, -1 for a size limit, -2 for a HIP error; fills err.
+int build_device_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
+                      const double* w, double k0, double k1, const PlanParams& pp,
+                      std::string& err);
+
+// Cut the target pairs of level L into chunks of consecutive targets with at
+// most chunk_pairs pairs each, group each chunk's pairs by cone slot and cut
+// them into tiles of at most 8 targets.
+void build_target_tiles(HostLevel& L, int64_t n, int64_t chunk_pairs);
+
 
 // Group the propagation pairs of parent level Pl (children at level L) by
 // child cone slot (requires npts <= 256).

@@ -86,6 +86,34 @@ def test_uneven_bodies_in_one_graph_fp32():
         op.close()
 
 
+def test_graph_branches_keep_each_operators_order():
+    """Copies of one operator hold different right-hand sides on parallel
+    branches of one graph; an operator listed twice keeps its two applies in
+    order on its own branch (they share its workspaces).  Every replay equals
+    the eager applies."""
+    from paper_2408_02274_amd import NMullerGraph, NMullerOperator
+    s = synth.cube_sphere(2, 8, 1.0)
+    _say("[gpu] graph branches: 3 copies of the config-1 operator, one listed twice")
+    ops = [NMullerOperator(s, 1.0, 2.25, tol=1e-3, max_nrhs=4) for _ in range(3)]
+    order = [0, 1, 2, 0]
+    ys = [torch.from_numpy(synth.complex_normal((4, 4, s.n), 40 + i)).to("cuda") for i in range(4)]
+    refs = [ops[k].apply(y) for k, y in zip(order, ys)]
+    outs = [torch.zeros_like(y) for y in ys]
+    g = NMullerGraph([ops[k] for k in order], ys, outs)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert _rel(o, r) < 1e-12, f"replay {rep}, entry {i}"
+        ops[1].apply(ys[0])                  # eager work between replays
+        torch.cuda.synchronize()
+    g.close()
+    for op in ops:
+        op.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_column_batches_equal_single_rhs(prec):
     """7 right-hand sides run as column batches (FP32: 4 + 2 + 1, FP64:

@@ -263,6 +263,28 @@ def test_lock_wait_give_up_is_reported():
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_target_chunks_do_not_change_the_sums(prec):
+    """The matrix-core target interpolation takes the targets of a level in
+    chunks of consecutive targets (bounded per-pair result buffer).  With
+    chunks of 997 pairs (dozens per level, most split inside a cone) the sums
+    equal those of one chunk per level: each target's pairs are summed in the
+    same order either way; only the propagation's LDS accumulation order may
+    differ between runs (FP64 1e-12, FP32 1e-6)."""
+    s, ks = CASES["sphere_c1"]()
+    w = np.random.default_rng(5).uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((1, 8, s.n), 6)
+    _say(f"[gpu] target chunks: n={s.n} precision={prec}")
+    big = _gpu_apply(s.x, s.normal, w, ks, phi, tol=1e-4, precision=prec)
+    small = _gpu_apply(s.x, s.normal, w, ks, phi, tol=1e-4, precision=prec, target_chunk_pairs=997)
+    from paper_2408_02274_amd import IFGFPlan
+    plan = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-4, precision=prec, target_chunk_pairs=997)
+    st = plan.stats()
+    plan.close()
+    assert all(L["target_path"] == "mfma_tiles" for L in st["levels"])
+    assert _rel(small, big) < (1e-12 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_long_body_with_deep_tree(prec):
     """The waveguide's rounded box (40 x 1 x 0.5 wavelengths, eps 12.1 / 2.1)
     on a coarse node grid (11,360 points): eleven levels, up to 512 x 1024 x

@@ -116,3 +116,59 @@ def test_dipole_excitation_matches_oracle():
     Eo0, Ho0 = excitation.dipole_fields(X, ke, 2.1, 2 * math.pi, p + 0.5j, np.zeros(3) + 5, np.zeros(3))
     assert np.linalg.norm(E0.cpu().numpy() - Eo0) < 1e-12 * np.linalg.norm(Eo0)
     assert np.linalg.norm(H0.cpu().numpy() - Ho0) < 1e-12 * np.linalg.norm(Ho0)
+
+
+CORRECTION_CASES = {
+    "sphere_nc8": lambda: synth.cube_sphere(2, 8, 1.0),
+    "ellipsoid_nc10": lambda: synth.ellipsoid(1.2, 0.8, 1.0, 3, 10),
+    "rounded_box_nc6": lambda: synth.rounded_box((1.0, 0.5, 0.25), 0.1, 0.2, 6),
+    "sphere_nc5": lambda: synth.cube_sphere(2, 5, 1.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CORRECTION_CASES))
+def test_device_corrections_equal_host_builder(case):
+    """The singular-pair search and quadrature of Sec. III-B/III-D/III-H built
+    on the device: the (target, patch) pairs equal the host builder's exactly
+    (same closest-point search, same operations, contraction off), and so
+    does the geometry of the quadrature, so that the weights differ only
+    through the last bits of sin and cos.  Bar 1e-11 of each (target, patch)
+    block's largest weight: one-ulp changes of every sin and cos move the host
+    builder's weights by 2e-13 at most, while rounding the geometry
+    differently (FMA contraction alone) moves the own-patch D weights by up to
+    5.7e-4 -- the innermost Fejer points lie ~1e-6 from the target, where
+    n . (x - y) cancels -- so this bar also checks the device's rounding."""
+    from paper_2408_02274_amd import NMullerOperator
+    s = CORRECTION_CASES[case]()
+    _say(f"[gpu] device vs host corrections: {case}, n = {s.n}")
+    host = NMullerOperator(s, 1.0, 2.25, tol=1e-4, corrections_on_host=1)
+    dev = NMullerOperator(s, 1.0, 2.25, tol=1e-4)
+    ih, idv = host.plan_info(), dev.plan_info()
+    _say(f"    host {ih}\n    device {idv}")
+    assert not ih["corrections_on_device"] and idv["corrections_on_device"]
+    ro_h, pp_h, v_h = host.corrections()
+    ro_d, pp_d, v_d = dev.corrections()
+    assert np.array_equal(ro_h, ro_d) and np.array_equal(pp_h, pp_d)
+    assert idv["correction_pairs"] == len(pp_h) > s.n
+    # each (target, patch) block against its own scale
+    vh = v_h.reshape(len(pp_h), -1)
+    vd = v_d.reshape(len(pp_d), -1)
+    blk = np.abs(vd - vh).max(axis=1) / np.abs(vh).max(axis=1)
+    glob = float(np.linalg.norm(vd - vh) / np.linalg.norm(vh))
+    _say(f"    weights: worst block {blk.max():.2e}, overall {glob:.2e}")
+    assert blk.max() < 1e-11 and glob < 1e-13
+    y = torch.from_numpy(synth.complex_normal((1, 4, s.n), 7)).to("cuda")
+    a_h = host.apply(y).cpu().numpy()
+    a_d = dev.apply(y).cpu().numpy()
+    host.close()
+    dev.close()
+    assert _rel(a_d, a_h) < 1e-12
+
+
+def test_unsupported_node_count_builds_corrections_on_host():
+    from paper_2408_02274_amd import NMullerOperator
+    s = synth.cube_sphere(1, 7, 1.0)
+    op = NMullerOperator(s, 1.0, 2.25, tol=1e-3)
+    info = op.plan_info()
+    op.close()
+    assert not info["corrections_on_device"] and info["correction_pairs"] > s.n
