@@ -239,7 +239,7 @@ def bodies32(log, reps=5, check=True):
     for i, (a, b, c, eps) in enumerate(synth.ellipsoid_batch(32, 1000)):
         npf = max(1, math.ceil(math.sqrt(area(a, b, c) / 1.5)))
         s = synth.ellipsoid(a, b, c, npf, 10)
-        ops.append(NMullerOperator(s, 1.0, eps, tol=1e-4, precision=B.IFGF_FP32))
+        ops.append(NMullerOperator(s, 1.0, eps, tol=1e-4, precision=B.IFGF_FP32, fp32_workspaces=1))
         ys.append(torch.from_numpy(synth.complex_normal((1, 4, s.n), 100 + i)).to("cuda"))
         outs.append(torch.empty_like(ys[-1]))
         npts.append(s.n)
@@ -726,8 +726,6 @@ def main():
     }
     if not args.no_batch and not args.ifgf_only:
         res["batching"] = batching(log)
-    if not args.no_bodies32 and not args.ifgf_only:
-        res["bodies32"] = bodies32(log, check=not args.no_cpu)
     if not args.no_cpu and not args.ifgf_only:
         # the oracle (O1) on the nodes of args.oracle_patches patches, and the
         # Mie error of the mixed GMRES solution, in the oracle's own program
@@ -771,8 +769,12 @@ def main():
             "o2_config1_seconds": o2s,
             "o2_note": f"reference IFGF (O2), one process, on the 1,536-point unit sphere at orders "
                        f"({st['Ps']}, {st['Pa']}); at this workload's size it would take hours"}
-    print(json.dumps(res), flush=True)
     op.close()
+    if not args.no_bodies32 and not args.ifgf_only:
+        import torch
+        torch.cuda.empty_cache()
+        res["bodies32"] = bodies32(log, check=not args.no_cpu)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -29,7 +29,14 @@ Readings where the text is silent or garbled:
       radial interpolation error grows with kappa H on large boxes);
   A5  neighbours are the 27 boxes with ||j - k||_inf <= 1 (self included);
   A6  cone intervals half-open with the last closed: index = min(floor, n-1),
-      phi = atan2(y, x) mapped to [0, 2 pi);
+      phi = atan2(y, x) mapped to [0, 2 pi); the angular indices are decided
+      against the boundary directions k pi / n_a (their C-library cos and
+      sin): theta >= k pi / n_a  <=>  cos theta <= cos(k pi / n_a), and phi
+      >= k pi / n_a  <=>  the point lies counter-clockwise of that boundary
+      ray, tested by a cross product in its half plane -- no acos or atan2
+      decides an index, so every implementation that forms the same
+      products takes the same decision, also for points exactly on a
+      boundary (which symmetric surfaces produce);
   A7  Chebyshev coefficients w_i = (2/n) c_i sum_j f(x_j) T_i(x_j), c_0 = 1/2,
       with n = P_s or P_a nodes on each cone interval;
   A8  normal derivative: the analytic derivative of the same interpolant by
@@ -81,12 +88,10 @@ def morton_key(k: np.ndarray) -> np.ndarray:
     return key
 
 
-# Discrete decisions (which cone holds a point) evaluate theta and phi with the
-# platform C library's acos/atan2 (Python's math module), and interpolation
-# points with its sin/cos.  Symmetric surfaces put points exactly on cone
-# boundaries (e.g. phi = 3 pi / 4 on a cube-sphere diagonal); numpy's vectorised
-# transcendental functions may round such ties differently from libm, and a
-# tie broken differently changes which interpolant serves a pair.
+# Interpolation points use the platform C library's sin/cos (Python's math
+# module) and the continuous (theta, phi) of a point its acos/atan2; the cone
+# index of a point is decided against tables of the boundary directions
+# (reading A6), computed with the same library.
 _acos = np.frompyfunc(math.acos, 1, 1)
 _atan2 = np.frompyfunc(math.atan2, 2, 1)
 _sin = np.frompyfunc(math.sin, 1, 1)
@@ -107,15 +112,38 @@ def spherical(dx, dy, dz):
     return r, th, ph
 
 
+def boundary_directions(na):
+    """cos and sin of the cone boundary angles k pi / na, k = 0..na."""
+    da = math.pi / na
+    return (np.array([math.cos(k * da) for k in range(na + 1)]),
+            np.array([math.sin(k * da) for k in range(na + 1)]))
+
+
 def cone_of(dx, dy, dz, h, ns, na):
-    """Cone segment index gamma = (i_s, i_theta, i_phi) flattened, plus (s, theta, phi)."""
+    """Cone segment index gamma = (i_s, i_theta, i_phi) flattened, plus (s, theta, phi).
+
+    i_s = min(floor(s / ds), ns - 1); i_theta counts the boundaries k = 1..na-1
+    with theta >= k pi / na, i.e. cos theta <= cos(k pi / na); i_phi counts
+    the boundaries phi >= k pi / na: in the upper half plane (y > 0, or y = 0
+    and x >= 0) those k = 1..na-1 whose boundary ray (cos, sin) has the
+    point on or counter-clockwise of it (cos_k y - sin_k x >= 0), in the
+    lower half the same test on the point turned by pi, plus na (reading A6).
+    A point on the z axis (x = y = 0) has i_phi = 0."""
     r, th, ph = spherical(dx, dy, dz)
     s = h / r
     ds = ETA / ns
-    da = math.pi / na
     i_s = np.minimum(np.floor(s / ds), ns - 1).astype(np.int64)
-    i_t = np.minimum(np.floor(th / da), na - 1).astype(np.int64)
-    i_p = np.minimum(np.floor(ph / da), 2 * na - 1).astype(np.int64)
+    ct = np.clip(dz / r, -1.0, 1.0)
+    C, S = boundary_directions(na)
+    Ck, Sk = C[None, 1:na], S[None, 1:na]
+    i_t = np.sum(np.atleast_1d(ct)[:, None] <= Ck, axis=1).astype(np.int64)
+    dx, dy = np.atleast_1d(dx), np.atleast_1d(dy)
+    up = (dy > 0) | ((dy == 0) & (dx >= 0))
+    px = np.where(up, dx, -dx)
+    py = np.where(up, dy, -dy)
+    i_p = np.sum(Ck * py[:, None] - Sk * px[:, None] >= 0, axis=1).astype(np.int64)
+    i_p = np.where(up, i_p, i_p + na)
+    i_p = np.where((dx == 0) & (dy == 0), 0, i_p)
     return (i_s * na + i_t) * (2 * na) + i_p, r, s, th, ph
 
 

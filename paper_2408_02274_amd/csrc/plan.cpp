@@ -6,10 +6,12 @@
 // level 3 (eq. rele_cone): a cone is relevant if it contains a cousin point
 // or an interpolation point of a relevant cone of the parent box.
 //
-// Geometric decisions (box of a point, cone of a point) are made here once,
-// in FP64, and handed to the device as integer tables, so that the GPU never
-// re-derives a discrete choice.  The arithmetic of those decisions follows
-// one fixed formula (see cone_index) with floating-point contraction off.
+// Geometric decisions (box of a point, cone of a point) are made once, in
+// FP64, and handed to the apply kernels as integer tables.  They use only
+// +, -, *, /, sqrt and floor, with floating-point contraction off, against
+// tables of the cone boundary directions (cone_index): any implementation
+// that forms the same products -- the oracle, the device planner -- takes
+// the same decision, also for points exactly on a cone boundary.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -25,25 +27,46 @@ static const double kTwoPi = 2.0 * 3.141592653589793;
 static const double kSqrt3 = std::sqrt(3.0);
 static const double kEta = std::sqrt(3.0) / 3.0;   // cone domain radius (Sec. III-F)
 
-int cone_index(double dx, double dy, double dz, double h, int ns, int na,
-               double* s_out, double* th_out, double* ph_out) {
-  double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-  double s = h / r;
+void cone_dirs(int na, std::vector<double>& C, std::vector<double>& S) {
+  const double da = kPi / na;
+  C.resize(na + 1);
+  S.resize(na + 1);
+  for (int k = 0; k <= na; ++k) {
+    C[k] = std::cos((double)k * da);
+    S[k] = std::sin((double)k * da);
+  }
+}
+
+int cone_index(double dx, double dy, double dz, double h, int ns, int na, const double* C, const double* S) {
+  const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+  const double s = h / r;
   double ct = dz / r;
   if (ct > 1.0) ct = 1.0;
   if (ct < -1.0) ct = -1.0;
-  double th = std::acos(ct);
-  double ph = std::atan2(dy, dx);
-  if (ph < 0.0) ph = ph + kTwoPi;
-  double ds = kEta / ns;
-  double da = kPi / na;
-  double fs = std::floor(s / ds), ft = std::floor(th / da), fp = std::floor(ph / da);
-  int64_t is = (int64_t)std::min(fs, (double)(ns - 1));
-  int64_t it = (int64_t)std::min(ft, (double)(na - 1));
-  int64_t ip = (int64_t)std::min(fp, (double)(2 * na - 1));
-  if (s_out) *s_out = s;
-  if (th_out) *th_out = th;
-  if (ph_out) *ph_out = ph;
+  const double ds = kEta / ns;
+  const double fs = std::floor(s / ds);
+  const int64_t is = (int64_t)std::min(fs, (double)(ns - 1));
+  // theta >= k da  <=>  cos theta <= C[k]: count k = 1..na-1 (C decreasing)
+  int lo = 1, hi = na;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (ct <= C[mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  const int64_t it = lo - 1;
+  // phi >= k da: the point on or counter-clockwise of boundary ray k, in its
+  // half plane (the lower half turned by pi)
+  const bool up = dy > 0.0 || (dy == 0.0 && dx >= 0.0);
+  const double px = up ? dx : -dx, py = up ? dy : -dy;
+  lo = 1;
+  hi = na;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] * py - S[mid] * px >= 0.0) lo = mid + 1;
+    else hi = mid;
+  }
+  int64_t ip = (lo - 1) + (up ? 0 : na);
+  if (dx == 0.0 && dy == 0.0) ip = 0;
   return (int)((is * na + it) * (2 * na) + ip);
 }
 
@@ -404,6 +427,10 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
   // relevant cones, top-down from level 3 (eq. rele_cone)
   for (int d = 3; d <= D; ++d) {
     HostLevel& L = P.lev[d];
+    std::vector<double> Cv, Sv;
+    cone_dirs(L.na, Cv, Sv);
+    const double* Cd = Cv.data();
+    const double* Sd = Sv.data();
     std::vector<std::vector<int32_t>> cones(L.nb);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t b = 0; b < L.nb; ++b) {
@@ -413,8 +440,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
         int32_t c = L.cous[e];
         for (int32_t i = L.start[c]; i < L.end[c]; ++i) {
           const double* xi = &P.xs[3 * i];
-          cl.push_back(cone_index(xi[0] - cb[0], xi[1] - cb[1], xi[2] - cb[2], L.h, L.ns, L.na,
-                                  nullptr, nullptr, nullptr));
+          cl.push_back(cone_index(xi[0] - cb[0], xi[1] - cb[1], xi[2] - cb[2], L.h, L.ns, L.na, Cd, Sd));
         }
       }
       if (d >= 4) {
@@ -425,8 +451,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
           for (int k = 0; k < npts; ++k) {
             double X[3];
             cone_point(Pl, cp, Pl.slot_cone[q], k, P.Ps, P.Pa, xs_, xa_, X);
-            cl.push_back(cone_index(X[0] - cb[0], X[1] - cb[1], X[2] - cb[2], L.h, L.ns, L.na,
-                                    nullptr, nullptr, nullptr));
+            cl.push_back(cone_index(X[0] - cb[0], X[1] - cb[1], X[2] - cb[2], L.h, L.ns, L.na, Cd, Sd));
           }
         }
       }
@@ -459,8 +484,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
       for (int32_t e = L.cous_off[T]; e < L.cous_off[T + 1]; ++e, ++o) {
         int32_t B = L.cous[e];
         const double* cb = &L.centers[3 * B];
-        int cone = cone_index(xi[0] - cb[0], xi[1] - cb[1], xi[2] - cb[2], L.h, L.ns, L.na,
-                              nullptr, nullptr, nullptr);
+        int cone = cone_index(xi[0] - cb[0], xi[1] - cb[1], xi[2] - cb[2], L.h, L.ns, L.na, Cd, Sd);
         int s = find_slot(L, B, cone);
         if (s < 0) ++bad;
         L.tp_slot[o] = s;
@@ -489,8 +513,7 @@ int build_host_plan(HostPlan& P, int64_t n, const double* x, const double* nrm,
           for (int k = 0; k < npts; ++k, ++o) {
             double X[3];
             cone_point(Pl, cp, Pl.slot_cone[q], k, P.Ps, P.Pa, xs_, xa_, X);
-            int cone = cone_index(X[0] - cc[0], X[1] - cc[1], X[2] - cc[2], L.h, L.ns, L.na,
-                                  nullptr, nullptr, nullptr);
+            int cone = cone_index(X[0] - cc[0], X[1] - cc[1], X[2] - cc[2], L.h, L.ns, L.na, Cd, Sd);
             int s = find_slot(L, c, cone);
             if (s < 0) ++bad2;
             Pl.pp_slot[o] = s;

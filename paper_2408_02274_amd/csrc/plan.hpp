@@ -117,9 +117,15 @@ void build_target_tiles(HostLevel& L, int64_t n, int64_t chunk_pairs);
 // child cone slot (requires npts <= 256).
 void build_prop_groups(HostLevel& Pl, const HostLevel& L, int npts);
 
+// cos and sin of the cone boundary angles k pi / na, k = 0..na.
+void cone_dirs(int na, std::vector<double>& C, std::vector<double>& S);
+
 // Cone index of the offset (dx,dy,dz) from a box centre (box radius h) with
-// ns x na x 2na cones; also returns s, theta, phi.
-int cone_index(double dx, double dy, double dz, double h, int ns, int na,
-               double* s, double* th, double* ph);
+// ns x na x 2na cones (Sec. III-F): i_s = min(floor(s / ds), ns - 1) with
+// s = h / r; i_theta counts the boundaries k = 1..na-1 with cos theta <= C[k];
+// i_phi counts those whose ray (C[k], S[k]) has the point on or
+// counter-clockwise of it, in the point's half plane (y > 0 or y = 0 <= x;
+// the lower half turned by pi, plus na); i_phi = 0 on the z axis.
+int cone_index(double dx, double dy, double dz, double h, int ns, int na, const double* C, const double* S);
 
 }  // namespace ifgf

@@ -19,6 +19,14 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
+def test_per_unit_flops_at_orders_4_6():
+    npts = 4 * 6 * 6
+    # (parent point, child box) pair: 16 complex columns x npts real weights, centring, geometry
+    assert bench.flops_per_unit("propagate", npts) == 9654.0
+    # (target, cousin box) pair: value and normal-derivative rows, weights, epilogue
+    assert bench.flops_per_unit("targets", npts) == 17868.0
+
+
 def test_per_unit_flops_at_orders_5_5():
     npts = 5 * 5 * 5
     # (parent point, child box) pair: 16 complex columns x npts real weights, centring, geometry
@@ -37,11 +45,11 @@ def test_traffic_summary_is_read_only_for_its_workload_and_kernel(monkeypatch):
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != bench.kernel_sha():
         pytest.skip("propagation source changed since the counters were taken")
-    t = bench.traffic_per_launch("propagate", "fp32", 153600, 5, 5)
+    t = bench.traffic_per_launch("propagate", "fp32", 153600, 4, 6)
     assert t == float(vals["hbm_bytes_per_launch"]) and t > 0
-    assert bench.traffic_per_launch("propagate", "fp64", 153600, 5, 5) is None
-    assert bench.traffic_per_launch("propagate", "fp32", 6144, 5, 5) is None
-    assert bench.traffic_per_launch("propagate", "fp32", 153600, 3, 5) is None
-    assert bench.traffic_per_launch("targets", "fp32", 153600, 5, 5) is None
-    monkeypatch.setattr(bench, "kernel_sha", lambda *a: "0" * 64)
+    assert bench.traffic_per_launch("propagate", "fp64", 153600, 4, 6) is None
+    assert bench.traffic_per_launch("propagate", "fp32", 6144, 4, 6) is None
     assert bench.traffic_per_launch("propagate", "fp32", 153600, 5, 5) is None
+    assert bench.traffic_per_launch("targets", "fp32", 153600, 4, 6) is None
+    monkeypatch.setattr(bench, "kernel_sha", lambda *a: "0" * 64)
+    assert bench.traffic_per_launch("propagate", "fp32", 153600, 4, 6) is None
