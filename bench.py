@@ -172,6 +172,17 @@ def batching(log, reps=5):
     gb = NMullerGraph(copies, [y[i * per:(i + 1) * per] for i in range(ncopy)],
                       [out[i * per:(i + 1) * per] for i in range(ncopy)])
     t_branch = clock(gb.launch)
+    # the same split launched eagerly, one HIP stream per copy (default priority)
+    streams = [torch.cuda.Stream() for _ in range(ncopy)]
+
+    def eager_streams():
+        torch.cuda.current_stream().synchronize()
+        for i, (c, st) in enumerate(zip(copies, streams)):
+            c.apply(y[i * per:(i + 1) * per], out[i * per:(i + 1) * per], stream=st.cuda_stream)
+        for st in streams:
+            st.synchronize()
+
+    t_streams = clock(eager_streams)
     ref = torch.empty_like(out)
     for i in range(64):
         op.apply(y[i:i + 1], ref[i:i + 1])
@@ -183,6 +194,7 @@ def batching(log, reps=5):
            "rhs_matvecs_per_s_graph": 64 / t_graph, "graph_nodes": g.nodes, "autotuned_columns": cols,
            "rhs_matvecs_per_s_graph_branches": 64 / t_branch, "graph_branches": ncopy,
            "graph_branches_vs_looped": t_loop / t_branch, "graph_branches_rel_dev": branch_dev,
+           "rhs_matvecs_per_s_streams": 64 / t_streams, "streams_vs_looped": t_loop / t_streams,
            "ms_looped": t_loop * 1e3, "ms_batched": t_batch * 1e3, "ms_graph": t_graph * 1e3,
            "ms_graph_branches": t_branch * 1e3}
     gb.close()

@@ -85,10 +85,10 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  *   targets of a level in chunks of consecutive targets holding at most this
  *   many pairs, so that the result buffer stays bounded (0 -> 1 GiB of FP64
  *   results, 2,396,745 pairs; the sums do not depend on it).
- * plan_on_device: 1 builds the plan tables (algorithm step 1: Morton order,
- *   boxes, neighbours, cousins, relevant cones, pair and tile lists) with
- *   kernels on the current device instead of the host; the tables are the
- *   same (ignored with host_only).
+ * plan_on_device: 1 (default) builds the plan tables (algorithm step 1:
+ *   Morton order, boxes, neighbours, cousins, relevant cones, pair and tile
+ *   lists) with kernels on the current device, 0 on the host; the tables are
+ *   the same bit for bit (host_only plans always use the host).
  * keep_pair_tables: 1 keeps host copies of the cousin-pair and
  *   propagation-pair cone slots after upload, for ifgf_plan_table.         */
 typedef struct {

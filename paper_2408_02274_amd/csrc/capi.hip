@@ -219,7 +219,7 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->verbose = 0;
   opt->deriv_mode = IFGF_DERIV_ANALYTIC;
   opt->target_chunk_pairs = 0;
-  opt->plan_on_device = 0;
+  opt->plan_on_device = 1;
   opt->keep_pair_tables = 0;
 }
 
