@@ -3,12 +3,13 @@
 rele_cone, cousin-pair and parent-point cone slots, propagation groups and
 tiles) against the host builder and the oracle.
 
-Bar: integer tables bit for bit (every decision is taken with the same
-formula and operation order; acos/atan2/sin/cos differ between the device
-and host libraries only in the last bit, which would move a point within
-~1e-16 of a cone boundary -- none of these inputs has one); the sums of plans
-built either way equal to 1e-12 (FP64; the propagation's LDS accumulation
-order is the only difference between runs).
+Bar: integer tables bit for bit.  Every decision is taken with the same
+formula and operation order, using only +, -, *, /, sqrt and floor against
+host-computed tables of the cone boundary directions and of the
+interpolation nodes' sines and cosines, so ties (the cube-sphere puts points
+exactly on cone boundaries) break the same way.  The sums of plans built
+either way agree to 1e-12 (FP64; the propagation's LDS accumulation order is
+the only difference between runs).
 """
 import math
 import time
