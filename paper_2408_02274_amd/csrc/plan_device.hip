@@ -654,6 +654,10 @@ int build_device_plan(HostPlan& P, int64_t n, const double* x, const double* nrm
       P.lev[d].ns = ns;
       P.lev[d].na = na;
       P.lev[d].ncones = (int64_t)ns * na * 2 * na;
+      if (P.lev[d].ncones >= ((int64_t)1 << 31)) {
+        err = "more than 2^31 cones per box at level " + std::to_string(d) + " (cone indices are 32-bit)";
+        return -1;
+      }
     }
   }
 

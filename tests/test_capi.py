@@ -153,3 +153,14 @@ def test_literal_radial_refinement_tables_equal_oracle():
         assert grew
     finally:
         binding.ifgf_destroy(h)
+
+
+def test_plan_refuses_more_cones_per_box_than_32_bit_indices_hold():
+    """Remark 2's doubling from level D up: a cloud 1,600 wavelengths across
+    has D = 14 and 2^11 x 2^12 x 2^13 cones per box at level 3; cone indices
+    are 32-bit, so the plan is refused before any table is built."""
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-800.0, 800.0, (50, 3))
+    n = np.tile([0.0, 0.0, 1.0], (50, 1))
+    with pytest.raises(binding.IFGFError, match="2\\^31 cones"):
+        binding.ifgf_plan(x, n, np.ones(50), 2 * math.pi, 2 * math.pi, 1e-3, host_only=1)
