@@ -330,7 +330,7 @@ def learned_preconditioner(log, seed=5003):
                   "converged": r[k]["converged"], "fallbacks": r[k]["fallbacks"]}
     out["learned_vs_plain_seconds"] = r["learned"]["wall"] / r["plain"]["wall"]
     out["learned_vs_scaling_only_seconds"] = r["learned"]["wall"] / r["scaling_only"]["wall"]
-    out["note"] = ("the network is judged against M = D^-1 alone, its fixed part: a ratio above 1 means the "
+    out["note"] = ("the network is compared with M = D^-1 alone, its fixed part: a ratio above 1 means the "
                    "learned correction costs time")
     out["config5_status"] = ("partial: trained on operator pairs (e i.i.d., r = A e) of ellipsoids with semi-axes "
                              "U[0.5, 2] and 21,600 points, evaluated on 4 held-out bodies, instead of solver pairs "
