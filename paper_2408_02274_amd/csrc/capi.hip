@@ -101,7 +101,7 @@ struct ifgf_plan_s {
   std::vector<TargetTiles> ttiles;      // ttiles[d]: target pairs by cone (matrix-core interpolation)
   // chunks of ttiles[d]: tiles [tc_tile[c], tc_tile[c+1]) hold targets [tc_i0[c], tc_i0[c+1])
   std::vector<std::vector<int64_t>> tc_tile, tc_i0;
-  void* d_res = nullptr;                // per-pair target contributions [pairs][28] complex
+  void* d_res = nullptr;                // per-pair target contributions [pairs][R][28] complex
   unsigned* d_err = nullptr;            // device error word (bit 0: a propagation lock wait gave up)
   int elem = 8;                         // bytes per real of the cone buffers and density copy
   int spin_limit = 1 << 22;             // attempts of the bounded lock wait
@@ -442,7 +442,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     }
   }
   if (max_pairs > 0) {
-    p->res_bytes = (size_t)p->elem * 56 * (size_t)max_pairs;
+    p->res_bytes = (size_t)p->elem * 56 * (size_t)max_pairs * p->rcap;
     p->d_res = ar.alloc(p->res_bytes);
     if (!p->d_res) {
       delete p;
@@ -508,7 +508,7 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
       T.end("leaf", ev, st, (double)H.leaf_pairs * R);
       for (int d = H.D; d >= 3; --d) {
         ev = T.begin(st);
-        if (R == 1 && p->d_res && p->ttiles[d].ntiles > 0) {
+        if (p->d_res && p->ttiles[d].ntiles > 0) {
           // cone-major tiles on the matrix cores, then the per-target sums,
           // one chunk of consecutive targets at a time (bounded result buffer)
           const std::vector<int64_t>& ct = p->tc_tile[d];
@@ -519,10 +519,10 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
             sub.start += ct[c];
             sub.cnt += ct[c];
             sub.ntiles = ct[c + 1] - ct[c];
-            if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, p->lev[d], p->ic, sub, p->d_xs, p->d_nrm, k0, k1,
+            if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->ic, sub, p->d_xs, p->d_nrm, k0, k1,
                                       p->d_vals[cur], p->d_res, p->opt.deriv_mode == IFGF_DERIV_FD, st)) !=
                     hipSuccess ||
-                (e = mf_targets_reduce(p->fp32, p->lev[d], ci[c], ci[c + 1], p->d_res, p->d_out_s, st)) !=
+                (e = mf_targets_reduce(p->fp32, p->lev[d], R, n, ci[c], ci[c + 1], p->d_res, p->d_out_s, st)) !=
                     hipSuccess)
               return set_hip_error(e, "targets");
           }

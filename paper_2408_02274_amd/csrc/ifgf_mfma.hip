@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
 // the interpolation weights at x + h n in the cone of x (extrapolating where
 // x + h n leaves it), and the normal derivative is (G(x + h n, x_B)
 // F(x + h n) - G(x, x_B) F(x)) / h, h = 1e-6.
-template <int PS, int PA, class T, bool FD>
+template <int PS, int PA, class T, bool FD, int R>
 __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, TargetTiles TT,
                                                       const double* __restrict__ xs,
                                                       const double* __restrict__ nrm, double k0, double k1,
@@ -924,21 +924,29 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   const int ct4 = 4 + (TC == 1 ? 0 : (gl & 1));
   const T g1 = FD ? kv * me[OLP + ct4] : kv * me[OLP + ct4] + kd * me[OPD + ct4];
   const T g2 = FD ? kd * me[OPD + ct4] : kd * me[OLP + ct4];
-  typename MF<T>::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-  const T* Vs = V + (int64_t)slot * K * 32 + 4 * lane;
+  typename MF<T>::acc c0[R], c1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) c0[r] = c1[r] = typename MF<T>::acc{0, 0, 0, 0};
+  // R right-hand sides: each cone row holds R groups of 32 values, pair jp
+  // of right-hand side r at (jp R + r) 256 reals (MFMA consumption order)
+  const T* Vs = V + (int64_t)slot * K * 32 * R + 4 * lane;
   // B operands of a pair of k-steps are requested PD - 1 pairs ahead of
   // their use (see the propagation kernel)
   using V4 = typename Vec4<T>::type;
   constexpr int NP = KSlot<PS, PA>::KS2 / 2;
   constexpr int PD = prop_prefetch(sizeof(T));
-  V4 ring[PD];
+  V4 ring[PD][R];
 #pragma unroll
-  for (int i = 0; i < PD - 1 && i < NP; ++i) ring[i] = *reinterpret_cast<const V4*>(Vs + (int64_t)i * 256);
+  for (int i = 0; i < PD - 1 && i < NP; ++i)
+#pragma unroll
+    for (int r = 0; r < R; ++r) ring[i][r] = *reinterpret_cast<const V4*>(Vs + (int64_t)(i * R + r) * 256);
 #pragma unroll
   for (int j = 0; j < KS; ++j) {
     const int jp = j >> 1;
     if ((j & 1) == 0 && jp + PD - 1 < NP)
-      ring[(jp + PD - 1) % PD] = *reinterpret_cast<const V4*>(Vs + (int64_t)(jp + PD - 1) * 256);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        ring[(jp + PD - 1) % PD][r] = *reinterpret_cast<const V4*>(Vs + (int64_t)((jp + PD - 1) * R + r) * 256);
     T av;
     if (j < NAB) {
       av = Ltv[j % PA] * U[j / PA] + Tdv[j % PA] * W[j / PA];   // (a, b) = j, phi-node gl
@@ -954,27 +962,39 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
         av = (T)0;
       }
     }
-    const V4& b4 = ring[jp % PD];
-    c0 = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0);
-    c1 = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const V4& b4 = ring[jp % PD][r];
+      c0[r] = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0[r]);
+      c1[r] = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1[r]);
+    }
     if (j & 1) __builtin_amdgcn_sched_barrier(0);
   }
   T(*ob)[33] = outb[wave];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int row = MF<T>::row(lane, e);
-    ob[row][r16] = c0[e];
-    ob[row][16 + r16] = c1[e];
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // epilogue: lane -> target lane / 8, density m = lane % 8, both kernels
+  // epilogue, one right-hand side at a time through the wavefront's LDS
+  // buffer: lane -> target lane / 8, density m = lane % 8, both kernels;
+  // results of right-hand side r at res[(e R + r) 56]
   const int tt = lane >> 3, m = lane & 7;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = MF<T>::row(lane, e);
+      ob[row][r16] = c0[r][e];
+      ob[row][16 + r16] = c1[r][e];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (tt < cnt) {
     const int64_t e = TT.e[kbeg + tt];
     const T* g = rw[tt] + OG;
-    T* out = res + e * 56;
+    T* out = res + (e * R + r) * 56;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int col = 8 * q + m;
@@ -998,24 +1018,29 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
       }
     }
   }
+  }
 }
 
-// out_s[i][k] += sum over the target pairs e of i of res[e - e0][k], k < 28,
-// for targets i0 <= i < i1 whose pairs start at e0 = tp_off[i0] (FP64 sums)
+// out_s[r][i][k] += sum over the target pairs e of i of res[(e - e0) R + r][k],
+// k < 28, for targets i0 <= i < i1 whose pairs start at e0 = tp_off[i0] and
+// right-hand sides r < R (FP64 sums; out_s holds n points per right-hand side)
 template <class T>
-__global__ void __launch_bounds__(256) k_targets_reduce(const int64_t* __restrict__ tp_off, int64_t i0, int64_t i1,
-                                                        const T* __restrict__ res, double2* __restrict__ out_s) {
+__global__ void __launch_bounds__(256) k_targets_reduce(const int64_t* __restrict__ tp_off, int64_t n, int64_t i0,
+                                                        int64_t i1, int R, const T* __restrict__ res,
+                                                        double2* __restrict__ out_s) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (i1 - i0) * 28) return;
-  const int64_t i = i0 + g / 28;
+  const int64_t per = (i1 - i0) * 28;
+  if (g >= per * R) return;
+  const int r = (int)(g / per);
+  const int64_t i = i0 + (g % per) / 28;
   const int k = (int)(g % 28);
   const int64_t e0 = tp_off[i0];
   double re = 0.0, im = 0.0;
   for (int64_t e = tp_off[i] - e0; e < tp_off[i + 1] - e0; ++e) {
-    re += (double)res[e * 56 + 2 * k];
-    im += (double)res[e * 56 + 2 * k + 1];
+    re += (double)res[(e * R + r) * 56 + 2 * k];
+    im += (double)res[(e * R + r) * 56 + 2 * k + 1];
   }
-  const int64_t o = i * 28 + k;
+  const int64_t o = (int64_t)r * 28 * n + i * 28 + k;
   const double2 v = out_s[o];
   out_s[o] = make_double2(v.x + re, v.y + im);
 }
@@ -1053,20 +1078,20 @@ hipError_t targets_t(const DevLevel& L, const InterpC& ic, const double* xs, con
                      k1, static_cast<const T*>(V), out_s);
   return hipGetLastError();
 }
-template <int PS, int PA, class T>
+template <int PS, int PA, class T, int R>
 hipError_t targets_tiles_t(const DevLevel& L, const InterpC& ic, const TargetTiles& TT, const double* xs,
                            const double* nrm, double k0, double k1, const void* V, void* res, bool fd,
                            hipStream_t st) {
   if (TT.ntiles <= 0) return hipSuccess;
   if (fd) {
-    if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, true>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT,
-                         xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+    if constexpr (std::is_same<T, double>::value && R == 1)
+      hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, true, 1>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic,
+                         TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
     else
-      return hipErrorInvalidValue;   // the forward difference is FP64 only
+      return hipErrorInvalidValue;   // the forward difference is FP64 with one right-hand side only
   } else {
-    hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, false>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic, TT,
-                       xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+    hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, false, R>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic,
+                       TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
   }
   return hipGetLastError();
 }
@@ -1135,11 +1160,13 @@ hipError_t dispatch_targets(int Ps, int Pa, int R, const DevLevel& L, const Inte
   });
 }
 template <class T>
-hipError_t dispatch_targets_tiles(int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
-                                  const double* xs, const double* nrm, double k0, double k1, const void* V,
-                                  void* res, bool fd, hipStream_t st) {
+hipError_t dispatch_targets_tiles(int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic,
+                                  const TargetTiles& TT, const double* xs, const double* nrm, double k0, double k1,
+                                  const void* V, void* res, bool fd, hipStream_t st) {
   return with_orders(Ps, Pa, [&]<int PS, int PA>() {
-    return targets_tiles_t<PS, PA, T>(L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
+    return with_columns<T>(R, [&]<int RR>() {
+      return targets_tiles_t<PS, PA, T, RR>(L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
+    });
   });
 }
 
@@ -1191,22 +1218,23 @@ hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const
               : dispatch_targets<double>(Ps, Pa, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
 }
 
-hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
-                            const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
-                            bool fd, hipStream_t st) {
-  return fp32 ? dispatch_targets_tiles<float>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st)
-              : dispatch_targets_tiles<double>(Ps, Pa, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
+hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic,
+                            const TargetTiles& TT, const double* xs, const double* nrm, double k0, double k1,
+                            const void* V, void* res, bool fd, hipStream_t st) {
+  return fp32 ? dispatch_targets_tiles<float>(Ps, Pa, R, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st)
+              : dispatch_targets_tiles<double>(Ps, Pa, R, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
 }
 
-hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t i0, int64_t i1, const void* res, double2* out_s,
-                             hipStream_t st) {
+hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int R, int64_t n, int64_t i0, int64_t i1, const void* res,
+                             double2* out_s, hipStream_t st) {
   if (i1 <= i0) return hipSuccess;
+  const unsigned nb = nblk((i1 - i0) * 28 * R, 256);
   if (fp32)
-    hipLaunchKernelGGL(k_targets_reduce<float>, dim3(nblk((i1 - i0) * 28, 256)), dim3(256), 0, st, L.tp_off, i0,
-                       i1, static_cast<const float*>(res), out_s);
+    hipLaunchKernelGGL(k_targets_reduce<float>, dim3(nb), dim3(256), 0, st, L.tp_off, n, i0, i1, R,
+                       static_cast<const float*>(res), out_s);
   else
-    hipLaunchKernelGGL(k_targets_reduce<double>, dim3(nblk((i1 - i0) * 28, 256)), dim3(256), 0, st, L.tp_off, i0,
-                       i1, static_cast<const double*>(res), out_s);
+    hipLaunchKernelGGL(k_targets_reduce<double>, dim3(nb), dim3(256), 0, st, L.tp_off, n, i0, i1, R,
+                       static_cast<const double*>(res), out_s);
   return hipGetLastError();
 }
 

@@ -52,16 +52,17 @@ hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const
                       const double* nrm, int64_t n, double k0, double k1, const void* V,
                       double2* out_s, hipStream_t st);
 
-// Target interpolation on the matrix cores (one right-hand side): per pair e
-// the 28 complex contributions into res [pairs][28] (complex in the cone
-// precision), then out_s[i] += sum of res over the pairs of target i.
+// Target interpolation on the matrix cores (R right-hand sides per pass): per pair e
+// the 28 complex contributions of each of R right-hand sides into res
+// [pairs][R][28] (complex in the cone precision), then out_s[r][i] += sum of
+// res over the pairs of target i.
 // fd: normal derivatives by the forward difference of the paper (FP64 only)
-hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, const DevLevel& L, const InterpC& ic, const TargetTiles& TT,
-                            const double* xs, const double* nrm, double k0, double k1, const void* V, void* res,
-                            bool fd, hipStream_t st);
-// out_s[i] += the per-pair results of targets i in [i0, i1), whose pairs
-// start at tp_off[i0] in res
-hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int64_t i0, int64_t i1, const void* res, double2* out_s,
-                             hipStream_t st);
+hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic,
+                            const TargetTiles& TT, const double* xs, const double* nrm, double k0, double k1,
+                            const void* V, void* res, bool fd, hipStream_t st);
+// out_s[r][i] += the per-pair results of targets i in [i0, i1), whose pairs
+// start at tp_off[i0] in res, for r < R (out_s holds n points per r)
+hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int R, int64_t n, int64_t i0, int64_t i1, const void* res,
+                             double2* out_s, hipStream_t st);
 
 }  // namespace ifgf
