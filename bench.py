@@ -305,6 +305,37 @@ def bodies32(log, reps=5, check=True):
     return res
 
 
+def one_kernel_per_pass(surf, eps, prec, tol, y, out_ref, value, steps, log):
+    """Remark 3 on the same workload: the operator rebuilt with one kernel per
+    IFGF pass (half the cone-buffer memory), its matvec rate against the
+    default mode's, and the deviation of its A y from the default's."""
+    import torch
+    from paper_2408_02274_amd import NMullerOperator
+    from paper_2408_02274_amd import binding as B
+    t0 = time.perf_counter()
+    op = NMullerOperator(surf, eps[0], eps[1], tol=tol, precision=prec, kernel_at_a_time=1)
+    plan_s = time.perf_counter() - t0
+    out = torch.empty_like(y)
+    op.apply(y, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op.apply(y, out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = B.ifgf_stats(op.ifgf_handle())
+    dev = float(torch.linalg.norm(out - out_ref) / torch.linalg.norm(out_ref))
+    op.close()
+    both, one = st["cone_buffer_bytes_by_mode"]
+    r = {"matvecs_per_s": steps / el, "ms_per_step": el / steps * 1e3,
+         "slowdown_vs_both_kernels": value / (steps / el), "plan_seconds": round(plan_s, 2),
+         "kernels_per_pass": st["kernels_per_pass"],
+         "cone_buffer_bytes": {"both_kernels": both, "one_kernel": one},
+         "rel_l2_vs_both_kernels": dev}
+    log(f"one kernel per pass: {r}")
+    return r
+
+
 def learned_preconditioner(log, seed=5003):
     """The learned FGMRES preconditioner on a held-out body of the family it
     was trained on (ellipsoid semi-axes U[0.5, 2], eps_r U[2, 12], 6 x 6 x 6
@@ -547,6 +578,8 @@ def main():
     ap.add_argument("--waveguide", action="store_true",
                     help="the 1.67M-point rounded-box waveguide workload instead (N-Mueller matvecs and "
                          "GMRES with the dipole excitation; ~10 minutes)")
+    ap.add_argument("--no-kat", action="store_true",
+                    help="skip the one-kernel-per-pass (Remark 3) measurement")
     ap.add_argument("--no-bodies32", action="store_true",
                     help="skip the 32-ellipsoid batch (config 3b; its plans and oracle checks take ~2 minutes)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -740,6 +773,9 @@ def main():
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in kern.items()},
     }
+    if not args.no_kat and not args.ifgf_only and args.nrhs == 1:
+        res["one_kernel_per_pass"] = one_kernel_per_pass(surf, (eps_e, eps_i), prec, args.tol, y, out_main,
+                                                         value, args.steps, log)
     if not args.no_batch and not args.ifgf_only:
         res["batching"] = batching(log)
     if not args.no_cpu and not args.ifgf_only:

@@ -90,7 +90,19 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  *   lists) with kernels on the current device, 0 on the host; the tables are
  *   the same bit for bit (host_only plans always use the host).
  * keep_pair_tables: 1 keeps host copies of the cousin-pair and
- *   propagation-pair cone slots after upload, for ifgf_plan_table.         */
+ *   propagation-pair cone slots after upload, for ifgf_plan_table.
+ * kernel_at_a_time (Remark 3): 0 (default) interpolates the 8 densities of
+ *   both kernels in one pass (IFGF_Vec); 1 runs one pass per kernel, with
+ *   half the cone-buffer memory and one right-hand side per pass; -1 picks
+ *   one pass per kernel at plan time when the cone buffers of both kernels
+ *   would exceed cone_memory_budget.  Needs the matrix-core orders (Pa = 5
+ *   or 6, 3 <= Ps <= 6), else IFGF_EINVAL.  The sums are the same either
+ *   way up to rounding; ifgf_stats reports the choice (kernels_per_pass)
+ *   and the cone-buffer bytes of both modes.
+ * cone_memory_budget: bytes the cone buffers may take when
+ *   kernel_at_a_time = -1; 0 = the free device memory at plan time less the
+ *   plan's other workspaces (a caller that allocates more afterwards, such
+ *   as the N-Mueller corrections, passes its own budget).                  */
 typedef struct {
   int Ps, Pa;
   int ns_init, na_init;
@@ -106,6 +118,8 @@ typedef struct {
   int64_t target_chunk_pairs;
   int plan_on_device;
   int keep_pair_tables;
+  int kernel_at_a_time;
+  int64_t cone_memory_budget;
 } ifgf_options;
 
 void ifgf_default_options(ifgf_options* opt);

@@ -35,7 +35,8 @@ class Options(C.Structure):
                 ("precision", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int),
                 ("batch_columns", C.c_int), ("fp32_workspaces", C.c_int), ("verbose", C.c_int),
                 ("deriv_mode", C.c_int), ("target_chunk_pairs", C.c_int64), ("plan_on_device", C.c_int),
-                ("keep_pair_tables", C.c_int)]
+                ("keep_pair_tables", C.c_int), ("kernel_at_a_time", C.c_int),
+                ("cone_memory_budget", C.c_int64)]
 
 
 class NMullerParams(C.Structure):

@@ -105,6 +105,7 @@ struct ifgf_plan_s {
   unsigned* d_err = nullptr;            // device error word (bit 0: a propagation lock wait gave up)
   int elem = 8;                         // bytes per real of the cone buffers and density copy
   int spin_limit = 1 << 22;             // attempts of the bounded lock wait
+  int nk = 2;                           // kernels per pass: 2 (both), or 1 (one at a time, Remark 3)
 };
 
 namespace ifgf {
@@ -120,10 +121,29 @@ namespace {
 // Which kernel interpolates onto the cousin targets of level d: the
 // matrix-core tiles (one right-hand side per pass; levels whose pair count
 // fits the tile tables) or one thread per target otherwise.
+// reals per cone row of the matrix-core buffers
+size_t row_width(const ifgf_plan_s* p) { return p->nk == 2 ? (size_t)32 * p->rcap : 16; }
+
 const char* target_path(const ifgf_plan_s* p, int d) {
   if (!p->mfma) return "generic";
   if (p->d_res && d < (int)p->ttiles.size() && p->ttiles[d].ntiles > 0) return "mfma_tiles";
   return "per_target";
+}
+
+// Bytes of the two cone buffers (level d uses buffer (D - d) & 1, each sized
+// for the largest of its levels) with nk kernels per pass and R right-hand
+// sides per pass: what Remark 3 computes from the relevant cone counts.
+size_t cone_buffer_bytes(const HostPlan& H, bool mfma, int elem, int R, int nk, int npts) {
+  int64_t slots[2] = {0, 0};
+  for (int d = 3; d <= H.D; ++d) slots[(H.D - d) & 1] = std::max(slots[(H.D - d) & 1], H.lev[d].nslots);
+  if (slots[0] == 0 && slots[1] == 0) return 0;
+  size_t total = 0;
+  for (int b = 0; b < 2; ++b) {
+    const size_t sl = (size_t)std::max<int64_t>(slots[b], 1);
+    total += mfma ? (size_t)elem * sl * kslot_rows(H.Ps, H.Pa, nk) * (nk == 2 ? 32 * R : 16)
+                  : sizeof(double2) * sl * npts * kCols;
+  }
+  return total;
 }
 
 int tol_to_orders(double tol, int* Ps, int* Pa) {
@@ -221,6 +241,8 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->target_chunk_pairs = 0;
   opt->plan_on_device = 1;
   opt->keep_pair_tables = 0;
+  opt->kernel_at_a_time = 0;
+  opt->cone_memory_budget = 0;
 }
 
 int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* normals,
@@ -250,6 +272,9 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     return set_error(IFGF_EINVAL, "deriv_mode must be IFGF_DERIV_ANALYTIC or IFGF_DERIV_FD");
   if (opt.deriv_mode == IFGF_DERIV_FD && (opt.precision != IFGF_FP64 || opt.max_nrhs > 1 || opt.batch_columns > 1))
     return set_error(IFGF_EINVAL, "IFGF_DERIV_FD needs IFGF_FP64 and one right-hand side per apply");
+  if (opt.kernel_at_a_time < -1 || opt.kernel_at_a_time > 1)
+    return set_error(IFGF_EINVAL, "kernel_at_a_time must be -1, 0 or 1");
+  if (opt.cone_memory_budget < 0) return set_error(IFGF_EINVAL, "cone_memory_budget must be >= 0");
 
   ifgf_plan_s* p = new (std::nothrow) ifgf_plan_s();
   if (!p) return set_error(IFGF_ENOMEM, "host allocation failed");
@@ -418,6 +443,33 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   p->rcap = p->mfma ? std::min(std::min(opt.max_nrhs, opt.batch_columns), max_batch_columns(p->fp32, opt.Ps, opt.Pa))
                     : 1;
   if (p->rcap == 3) p->rcap = 2;
+  p->elem = (p->fp32 && opt.fp32_workspaces) ? 4 : 8;
+  // Kernels per pass (Remark 3): both, or one at a time with half the cone
+  // memory.  -1 picks one at a time when the cone buffers of both kernels
+  // exceed the budget: cone_memory_budget, else the free device memory less
+  // the workspaces still to be allocated.
+  if (opt.kernel_at_a_time != 0) {
+    if (!p->mfma) {
+      delete p;
+      return set_error(IFGF_EINVAL, "kernel_at_a_time needs the matrix-core orders (Pa = 5 or 6, 3 <= Ps <= 6)");
+    }
+    p->nk = 1;
+    if (opt.kernel_at_a_time == -1) {
+      size_t budget = (size_t)opt.cone_memory_budget;
+      if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipError_t e = hipMemGetInfo(&fr, &tot); e != hipSuccess) {
+          delete p;
+          return set_hip_error(e, "hipMemGetInfo");
+        }
+        const size_t rest = sizeof(double2) * n * (kNS + (size_t)kOut * p->rcap) + (size_t)p->elem * 16 * n * p->rcap +
+                            (size_t)p->elem * 56 * (size_t)max_pairs * p->rcap;
+        budget = fr > rest ? fr - rest : 0;
+      }
+      p->nk = cone_buffer_bytes(H, true, p->elem, p->rcap, 2, p->ic.npts) > budget ? 1 : 2;
+    }
+    if (p->nk == 1) p->rcap = 1;
+  }
   p->rsel = p->rcap;
   p->d_a = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kNS));
   p->d_out_s = static_cast<double2*>(ar.alloc(sizeof(double2) * n * kOut * p->rcap));
@@ -433,7 +485,6 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   // A matrix-core plan can run in either precision (ifgf_set_precision), so
   // its density copy and cone buffers are sized for FP64 -- unless it was
   // built FP32-only (fp32_workspaces), which halves them.
-  p->elem = (p->fp32 && opt.fp32_workspaces) ? 4 : 8;
   if (p->mfma) {
     p->d_af = ar.alloc((size_t)p->elem * 16 * (size_t)n * p->rcap);
     if (!p->d_af) {
@@ -442,7 +493,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     }
   }
   if (max_pairs > 0) {
-    p->res_bytes = (size_t)p->elem * 56 * (size_t)max_pairs * p->rcap;
+    p->res_bytes = (size_t)p->elem * 28 * p->nk * (size_t)max_pairs * p->rcap;
     p->d_res = ar.alloc(p->res_bytes);
     if (!p->d_res) {
       delete p;
@@ -452,7 +503,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
   if (p->max_slots > 0) {
     for (int b = 0; b < 2; ++b) {
       const size_t slots = (size_t)std::max<int64_t>(p->par_slots[b], 1);
-      const size_t vb = p->mfma ? (size_t)p->elem * slots * kslot_rows(opt.Ps, opt.Pa) * 32 * p->rcap
+      const size_t vb = p->mfma ? (size_t)p->elem * slots * kslot_rows(opt.Ps, opt.Pa, p->nk) * row_width(p)
                                 : sizeof(double2) * slots * p->ic.npts * kCols;
       p->d_vals[b] = static_cast<double2*>(ar.alloc(vb));
       p->vals_bytes += vb;
@@ -500,10 +551,15 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
       }
       if ((e = mf_gather(p->fp32, R, dens, p->d_perm, p->d_w, n, p->d_af, st)) != hipSuccess)
         return set_hip_error(e, "gather batch");
+      // both kernels in one pass (nk = 2), or one pass per kernel (nk = 1,
+      // Remark 3): pass kq runs the kernel of wavenumber k_kq alone
+      const int nk = p->nk;
+      for (int kq = 0; kq < 3 - nk; ++kq) {
+      const double ka = nk == 2 ? k0 : H.k[kq], kb = nk == 2 ? k1 : H.k[kq];
       int cur = 0;
       hipEvent_t ev = T.begin(st);
-      if ((e = mf_leaf(p->fp32, H.Ps, H.Pa, R, p->lev[H.D], p->ic, p->d_xs, p->d_af, k0, k1, p->d_vals[cur], st)) !=
-          hipSuccess)
+      if ((e = mf_leaf(p->fp32, H.Ps, H.Pa, R, nk, p->lev[H.D], p->ic, p->d_xs, p->d_af, ka, kb, p->d_vals[cur],
+                       st)) != hipSuccess)
         return set_hip_error(e, "leaf");
       T.end("leaf", ev, st, (double)H.leaf_pairs * R);
       for (int d = H.D; d >= 3; --d) {
@@ -519,30 +575,31 @@ int ifgf_apply(ifgf_plan_t p, const void* densities, int nrhs, void* out, void* 
             sub.start += ct[c];
             sub.cnt += ct[c];
             sub.ntiles = ct[c + 1] - ct[c];
-            if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->ic, sub, p->d_xs, p->d_nrm, k0, k1,
+            if ((e = mf_targets_tiles(p->fp32, H.Ps, H.Pa, R, nk, p->lev[d], p->ic, sub, p->d_xs, p->d_nrm, ka, kb,
                                       p->d_vals[cur], p->d_res, p->opt.deriv_mode == IFGF_DERIV_FD, st)) !=
                     hipSuccess ||
-                (e = mf_targets_reduce(p->fp32, p->lev[d], R, n, ci[c], ci[c + 1], p->d_res, p->d_out_s, st)) !=
-                    hipSuccess)
+                (e = mf_targets_reduce(p->fp32, p->lev[d], R, nk, kq, n, ci[c], ci[c + 1], p->d_res, p->d_out_s,
+                                       st)) != hipSuccess)
               return set_hip_error(e, "targets");
           }
-        } else if ((e = mf_targets(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, k0, k1,
-                                   p->d_vals[cur], p->d_out_s, st)) != hipSuccess) {
+        } else if ((e = mf_targets(p->fp32, H.Ps, H.Pa, R, nk, p->lev[d], p->ic, p->d_xs, p->d_nrm, n, ka, kb,
+                                   p->d_vals[cur], p->d_out_s, kq, st)) != hipSuccess) {
           return set_hip_error(e, "targets");
         }
         T.end("targets", ev, st, (double)H.lev[d].tp_off.back() * R);
         if (d > 3) {
           ev = T.begin(st);
-          if ((e = mf_propagate(p->fp32, H.Ps, H.Pa, R, p->lev[d], p->lev[d - 1], p->ic, p->groups[d - 1], k0,
-                                k1, p->d_vals[cur], p->d_vals[cur ^ 1], p->spin_limit, p->d_err, st)) !=
+          if ((e = mf_propagate(p->fp32, H.Ps, H.Pa, R, nk, p->lev[d], p->lev[d - 1], p->ic, p->groups[d - 1], ka,
+                                kb, p->d_vals[cur], p->d_vals[cur ^ 1], p->spin_limit, p->d_err, st)) !=
               hipSuccess)
             return set_hip_error(e, "propagate");
           T.end("propagate", ev, st, (double)H.lev[d - 1].pp_off.back() * R);
           cur ^= 1;
         }
       }
+      }
       for (int r = 0; r < R; ++r) {
-        ev = T.begin(st);
+        hipEvent_t ev = T.begin(st);
         double2* o = static_cast<double2*>(out) + (int64_t)(r0 + r) * kOut * n;
         if ((e = launch_scatter_out(p->d_out_s + (int64_t)r * kOut * n, p->d_perm, n, o, st)) != hipSuccess)
           return set_hip_error(e, "scatter");
@@ -658,6 +715,11 @@ int ifgf_stats(ifgf_plan_t p, char* json, size_t cap) {
                   ",\"device_bytes\":" + std::to_string(p->arena.bytes()) +
                   ",\"workspace_elem_bytes\":" + std::to_string(p->elem) +
                   ",\"cone_buffer_bytes\":" + std::to_string(p->vals_bytes) +
+                  ",\"kernels_per_pass\":" + std::to_string(p->opt.host_only ? 0 : p->nk) +
+                  ",\"cone_buffer_bytes_by_mode\":[" +
+                  std::to_string(cone_buffer_bytes(H, mfma_path_supported(H.Ps, H.Pa), 8, 1, 2, p->ic.npts)) + "," +
+                  std::to_string(mfma_path_supported(H.Ps, H.Pa)
+                                     ? cone_buffer_bytes(H, true, 8, 1, 1, p->ic.npts) : (size_t)0) + "]" +
                   ",\"target_result_bytes\":" + std::to_string(p->res_bytes) + ",\"levels\":[";
   for (int d = 3; d <= H.D; ++d) {
     const HostLevel& L = H.lev[d];
@@ -695,7 +757,7 @@ int ifgf_autotune(ifgf_plan_t p, void* stream, int* chosen) {
   if (p->timer.on) return set_error(IFGF_EINVAL, "switch per-kernel timing off before tuning");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t n = p->host.n;
-  const int top = std::min(p->rcap, max_batch_columns(p->fp32, p->host.Ps, p->host.Pa));
+  const int top = p->nk == 1 ? 1 : std::min(p->rcap, max_batch_columns(p->fp32, p->host.Ps, p->host.Pa));
   int best = 1;
   if (p->mfma && top > 1) {
     DeviceArena tmp;

@@ -26,6 +26,16 @@
 // (FP32) load per lane feeds four MFMAs and a wavefront reads 1 KB of
 // contiguous memory per load.
 //
+// One kernel at a time (Remark 3): a pass carries the 8 densities of one of
+// the two kernels only, so a row holds 16 reals (the real parts of the 8
+// complex columns, then their imaginary parts) and the cone buffers take half
+// the memory.  The rows are padded to a multiple of four k-steps (K1 rows)
+// and stored in consumption order per quad of k-steps (see kofs1): lane
+// l = 16 g + c finds (row 4 j + g, column c) for the four k-steps j of a quad
+// in four consecutive reals.  The real and imaginary parts of a column then
+// come out of one MFMA in lanes c and c + 8, which swap them for the complex
+// factors of the epilogues.
+//
 // The interpolant is the tensor Chebyshev interpolant of Sec. III-F in
 // Lagrange form on the same nodes (identical polynomial).  Geometry is
 // evaluated in cone-centred coordinates so that FP32 keeps relative accuracy:
@@ -180,6 +190,8 @@ template <int PS, int PA> struct KSlot {
   static constexpr int KS = NAB + (TC * NAB + 3) / 4;   // k-steps that carry nodes
   static constexpr int KS2 = KS + (KS & 1);         // k-steps stored (even)
   static constexpr int K = 4 * KS2;                 // rows stored per cone
+  static constexpr int KS4 = (KS + 3) & ~3;         // k-steps stored, one kernel per pass
+  static constexpr int K1 = 4 * KS4;                // rows stored per cone, one kernel per pass
   static constexpr int NPTS = NAB * PA;
 };
 
@@ -194,24 +206,34 @@ __device__ __forceinline__ int kofs(int row, int col) {
   return (((j >> 1) * R + r) * 64 + 16 * g + c) * 4 + 2 * (j & 1) + h;
 }
 
+// Offset of (row, column) within one cone of a one-kernel pass (16 reals
+// per row): k-step quad j / 4, lane 16 (row mod 4) + column, then k-step
+// j mod 4.
+__device__ __forceinline__ int kofs1(int row, int col) {
+  const int j = row >> 2, g = row & 3;
+  return ((j >> 2) * 64 + 16 * g + col) * 4 + (j & 3);
+}
+
 template <class T> struct Vec4;
 template <> struct Vec4<float> { using type = f4v; };
 template <> struct Vec4<double> { using type = d4v; };
 
-// LDS of the propagation kernel: accumulator, per-wavefront geometry records
-// (4 wavefronts x 16 rows x tb tiles x (10 + 2 Pa) values), parent-point
-// geometry, lock
-constexpr int64_t prop_lds_bytes_tb(int Ps, int Pa, int R, int elem, int tb) {
-  return (int64_t)Ps * Pa * Pa * (32 * R + 1) * elem + 4 * 16 * tb * (10 + 2 * Pa) * elem +
+// reals per cone row: R groups of 32 (both kernels), or 16 (one kernel)
+constexpr int row_reals(int R, int NK) { return NK == 2 ? 32 * R : 16; }
+// LDS of the propagation kernel: accumulator (W reals per point), per-wavefront
+// geometry records (4 wavefronts x 16 rows x tb tiles x (10 + 2 Pa) values),
+// parent-point geometry, lock
+constexpr int64_t prop_lds_bytes_tb(int Ps, int Pa, int W, int elem, int tb) {
+  return (int64_t)Ps * Pa * Pa * (W + 1) * elem + 4 * 16 * tb * (10 + 2 * Pa) * elem +
          (int64_t)Ps * Pa * Pa * 4 * elem + 4;
 }
 // Tiles a wavefront prepares per geometry phase: 4, or 2 where that keeps an
 // FP64 block within 80 KB of LDS (two blocks per compute unit).
-constexpr int prop_tiles_per_batch(int Ps, int Pa, int R, int elem) {
-  return (elem == 8 && prop_lds_bytes_tb(Ps, Pa, R, elem, 4) > 80 * 1024) ? 2 : 4;
+constexpr int prop_tiles_per_batch(int Ps, int Pa, int W, int elem) {
+  return (elem == 8 && prop_lds_bytes_tb(Ps, Pa, W, elem, 4) > 80 * 1024) ? 2 : 4;
 }
-constexpr int64_t prop_lds_bytes(int Ps, int Pa, int R, int elem) {
-  return prop_lds_bytes_tb(Ps, Pa, R, elem, prop_tiles_per_batch(Ps, Pa, R, elem));
+constexpr int64_t prop_lds_bytes(int Ps, int Pa, int W, int elem) {
+  return prop_lds_bytes_tb(Ps, Pa, W, elem, prop_tiles_per_batch(Ps, Pa, W, elem));
 }
 constexpr int64_t kLdsLimit = 160 * 1024;
 // pairs of k-steps whose B operands a propagation wavefront keeps in flight
@@ -248,25 +270,32 @@ __global__ void k_gather(const double2* __restrict__ dens, const int64_t* __rest
   a[2 * t + 1] = (T)(v.y * w[i]);
 }
 
-// leaf cone values: thread per (slot, row, right-hand side)
-template <int PS, int PA, class T, int R>
+// leaf cone values: thread per (slot, row, right-hand side).  NK = 1: the
+// 8 columns of kernel k0 only (one kernel per pass).
+template <int PS, int PA, class T, int R, int NK>
 __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const double* __restrict__ xs, const T* __restrict__ a,
                          double k0, double k1, T* __restrict__ V) {
   constexpr int NAB = KSlot<PS, PA>::NAB;
-  constexpr int K = KSlot<PS, PA>::K;
+  constexpr int K = NK == 2 ? KSlot<PS, PA>::K : KSlot<PS, PA>::K1;
+  constexpr int W = row_reals(R, NK);
   int64_t t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= L.nslots * K * R) return;
   int64_t q = t / (K * R);
   int row = (int)((t / R) % K);
   const int r = (int)(t % R);
-  // column c (real part) and 16 + c (imaginary part) sit side by side
-  T* o = V + q * (int64_t)K * 32 * R + kofs<R>(row, 32 * r);
+  // NK = 2: column c (real part) and 16 + c (imaginary part) sit side by
+  // side; NK = 1: column c of the 16 reals at o[4 c]
+  T* o = V + q * (int64_t)K * W + (NK == 2 ? kofs<R>(row, 32 * r) : kofs1(row, 0));
   int p = point_of_row<PA>(row, NAB);
   if (p < 0) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      o[4 * c] = (T)0;
-      o[4 * c + 1] = (T)0;
+      if constexpr (NK == 2) {
+        o[4 * c] = (T)0;
+        o[4 * c + 1] = (T)0;
+      } else {
+        o[4 * c] = (T)0;
+      }
     }
     return;
   }
@@ -276,9 +305,9 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
   cone_node<PA, T>(L.ns, L.na, L.slot_cone[q], p, ic, &s, &ux, &uy, &uz);
   const T rxc = (T)L.h / s;
   const T Yx = rxc * ux, Yy = rxc * uy, Yz = rxc * uz;
-  T acc[32];
+  T acc[16 * NK];
 #pragma unroll
-  for (int m = 0; m < 32; ++m) acc[m] = (T)0;
+  for (int m = 0; m < 16 * NK; ++m) acc[m] = (T)0;
   const T kk[2] = {(T)k0, (T)k1};
   for (int32_t j = L.start[b]; j < L.end[b]; ++j) {
     const T yx = (T)(xs[3 * j] - c[0]), yy = (T)(xs[3 * j + 1] - c[1]), yz = (T)(xs[3 * j + 2] - c[2]);
@@ -288,7 +317,7 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
     const T ratio = rxc / rxy;
     const T* aj = a + ((int64_t)j * R + r) * 16;
 #pragma unroll
-    for (int qq = 0; qq < 2; ++qq) {
+    for (int qq = 0; qq < NK; ++qq) {
       T sn, cs;
       tsincos<T>(kk[qq] * diff, &sn, &cs);
       const T gr = ratio * cs, gi = ratio * sn;
@@ -296,14 +325,18 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
       for (int m = 0; m < 8; ++m) {
         const T ar = aj[2 * m], ai = aj[2 * m + 1];
         acc[qq * 8 + m] += gr * ar - gi * ai;
-        acc[16 + qq * 8 + m] += gr * ai + gi * ar;
+        acc[8 * NK + qq * 8 + m] += gr * ai + gi * ar;
       }
     }
   }
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    o[4 * c] = acc[c];
-    o[4 * c + 1] = acc[16 + c];
+    if constexpr (NK == 2) {
+      o[4 * c] = acc[c];
+      o[4 * c + 1] = acc[16 + c];
+    } else {
+      o[4 * c] = acc[c];
+    }
   }
 }
 
@@ -313,8 +346,8 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
 // wavefronts.  A wavefront takes its tiles TB (4, or 2 for large FP64 cones)
 // at a time: one lane per point evaluates the child-cone coordinates,
 // Lagrange factors and re-centring factor of its point into wave-private LDS,
-// then the TB MFMA tiles run.
-template <int PS, int PA, class T, int R>
+// then the TB MFMA tiles run.  NK = 1: one kernel per pass (wavenumber k0).
+template <int PS, int PA, class T, int R, int NK>
 __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, InterpC ic, PropGroups G,
                                                    double k0, double k1, const T* __restrict__ Vc,
                                                    T* __restrict__ Vp, int spin_limit,
@@ -322,14 +355,13 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   constexpr int NAB = KSlot<PS, PA>::NAB;
   constexpr int TC = KSlot<PS, PA>::TC;
   constexpr int KS = KSlot<PS, PA>::KS;
-  constexpr int KS2 = KSlot<PS, PA>::KS2;
-  constexpr int K = KSlot<PS, PA>::K;
+  constexpr int K = NK == 2 ? KSlot<PS, PA>::K : KSlot<PS, PA>::K1;
   constexpr int NPTS = KSlot<PS, PA>::NPTS;
   // per-lane geometry record: Ls [0, PS), Lt [OT, OT + PA), Lp [OP, OP + PA),
   // re-centring factors [OF, OF + 4)
   constexpr int OT = 6, OP = OT + PA, OF = OP + PA, GW = OF + 4;
-  constexpr int W = 32 * R;             // reals per cone row
-  constexpr int TB = prop_tiles_per_batch(PS, PA, R, sizeof(T));
+  constexpr int W = row_reals(R, NK);   // reals per cone row
+  constexpr int TB = prop_tiles_per_batch(PS, PA, W, sizeof(T));
   __shared__ T acc[NPTS][W + 1];
   __shared__ T gbuf[4][16 * TB][GW];    // per wavefront: TB tiles x 16 rows
   __shared__ T geo[NPTS][4];            // parent points about the parent centre, and r_p
@@ -374,13 +406,14 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
     mine = (gl < TB && tl < t_end) ? G.rec[tl] : make_int4(0, 0, 0, 0);
   }
   // B operands: one 16-byte (FP32) load per lane and right-hand side per
-  // pair of k-steps, issued PD - 1 pairs ahead of its use into a ring of
-  // registers; a scheduling barrier after each pair keeps the compiler from
-  // sinking the loads next to their use (an L2 hit takes far longer than the
-  // MFMAs of one pair).  The first pairs of a tile are requested before the
-  // epilogue of the tile before it.
+  // pair of k-steps (NK = 1: per quad of k-steps), issued PD - 1 loads ahead
+  // of its use into a ring of registers; a scheduling barrier after each
+  // load's k-steps keeps the compiler from sinking the loads next to their
+  // use (an L2 hit takes far longer than the MFMAs they feed).  The first
+  // loads of a tile are requested before the epilogue of the tile before it.
   using V4 = typename Vec4<T>::type;
-  constexpr int NP = KS2 / 2;
+  constexpr int SPL = NK == 2 ? 2 : 4;  // k-steps per load
+  constexpr int NP = NK == 2 ? KSlot<PS, PA>::KS2 / 2 : KSlot<PS, PA>::KS4 / 4;
   constexpr int PD = prop_prefetch(sizeof(T));
   V4 ring[PD][R];
   auto first_pairs = [&](int32_t child_slot) {
@@ -448,7 +481,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
         const T diff = (dx * dx + dy * dy + dz * dz - (T)2 * (Yx * dx + Yy * dy + Yz * dz)) / (rc + rp);
         const T ratio = rp * rci;
 #pragma unroll
-        for (int qq = 0; qq < 2; ++qq) {
+        for (int qq = 0; qq < NK; ++qq) {
           T sn, cs;
           tsincos<T>(kk[qq] * diff, &sn, &cs);
           gb[lane][OF + 2 * qq] = ratio * cs;
@@ -493,8 +526,8 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
       }
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
-        const int jp = j >> 1;
-        if ((j & 1) == 0 && jp + PD - 1 < NP) {
+        const int jp = j / SPL;
+        if (j % SPL == 0 && jp + PD - 1 < NP) {
 #pragma unroll
           for (int r = 0; r < R; ++r)
             ring[(jp + PD - 1) % PD][r] = *reinterpret_cast<const V4*>(Vs + (int64_t)((jp + PD - 1) * R + r) * 256);
@@ -520,17 +553,29 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const V4& b4 = ring[jp % PD][r];
-          c0[r] = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0[r]);
-          c1[r] = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1[r]);
+          if constexpr (NK == 2) {
+            c0[r] = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0[r]);
+            c1[r] = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1[r]);
+          } else {
+            c0[r] = MF<T>::mma(av, b4[j & 3], c0[r]);
+          }
         }
-        if (j & 1) __builtin_amdgcn_sched_barrier(0);
+        if (j % SPL == SPL - 1) __builtin_amdgcn_sched_barrier(0);
       }
       // the next tile (of this batch, else the first of the next batch)
       if (b + 1 < nb) first_pairs(rb[b + 1 < TB ? b + 1 : 0].x);
       else if (nn > 0) first_pairs(rn[0].x);
       __builtin_amdgcn_sched_barrier(0);
-      // lane holds rows MF::row(lane, e), complex column r16 (kernel r16 / 8)
-      const int qq = r16 >> 3;
+      // NK = 2: lane holds rows MF::row(lane, e), complex column r16 (kernel
+      // r16 / 8) in c0 (real) and c1 (imaginary part).  NK = 1: lane holds
+      // real column r16 of kernel k0 in c0; lanes r16 < 8 hold real parts,
+      // lanes r16 + 8 the imaginary parts of the same columns
+      const int qq = NK == 2 ? r16 >> 3 : 0;
+      if constexpr (NK == 1) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c1[0][e] = __shfl_xor(c0[0][e], 8);
+      }
+      const bool re_lane = r16 < 8;
       if constexpr (sizeof(T) == 4) {
         int po[4];
         T zr[4][R], zi[4][R];
@@ -542,9 +587,15 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
           const T fr = gb[16 * b + ro][OF + 2 * qq], fi = gb[16 * b + ro][OF + 1 + 2 * qq];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            const T vr = c0[r][e], vi = c1[r][e];
-            zr[e][r] = fr * vr - fi * vi;
-            zi[e][r] = fr * vi + fi * vr;
+            if constexpr (NK == 2) {
+              const T vr = c0[r][e], vi = c1[r][e];
+              zr[e][r] = fr * vr - fi * vi;
+              zi[e][r] = fr * vi + fi * vr;
+            } else {
+              // own value and the partner lane's: (re, im) of column r16 mod 8
+              const T vr = re_lane ? c0[r][e] : c1[r][e], vi = re_lane ? c1[r][e] : c0[r][e];
+              zr[e][r] = re_lane ? fr * vr - fi * vi : fr * vi + fi * vr;
+            }
           }
         }
         // The rows of one tile are distinct parent points, so the tile is added
@@ -580,7 +631,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 #pragma unroll
               for (int r = 0; r < R; ++r) {
                 oldr[e][r] = acc[po[e]][32 * r + r16];
-                oldi[e][r] = acc[po[e]][32 * r + 16 + r16];
+                if constexpr (NK == 2) oldi[e][r] = acc[po[e]][32 * r + 16 + r16];
               }
             }
           }
@@ -590,7 +641,7 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 #pragma unroll
               for (int r = 0; r < R; ++r) {
                 acc[po[e]][32 * r + r16] = oldr[e][r] + zr[e][r];
-                acc[po[e]][32 * r + 16 + r16] = oldi[e][r] + zi[e][r];
+                if constexpr (NK == 2) acc[po[e]][32 * r + 16 + r16] = oldi[e][r] + zi[e][r];
               }
             }
           }
@@ -609,9 +660,14 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
             const T fr = gb[16 * b + orow][OF + 2 * qq], fi = gb[16 * b + orow][OF + 1 + 2 * qq];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-              const T vr = c0[r][e], vi = c1[r][e];
-              atomicAdd(&acc[pe][32 * r + r16], fr * vr - fi * vi);
-              atomicAdd(&acc[pe][32 * r + 16 + r16], fr * vi + fi * vr);
+              if constexpr (NK == 2) {
+                const T vr = c0[r][e], vi = c1[r][e];
+                atomicAdd(&acc[pe][32 * r + r16], fr * vr - fi * vi);
+                atomicAdd(&acc[pe][32 * r + 16 + r16], fr * vi + fi * vr);
+              } else {
+                const T vr = re_lane ? c0[r][e] : c1[r][e], vi = re_lane ? c1[r][e] : c0[r][e];
+                atomicAdd(&acc[pe][r16], re_lane ? fr * vr - fi * vi : fr * vi + fi * vr);
+              }
             }
           }
         }
@@ -627,10 +683,17 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
   // contiguous stores in consumption order: offset i -> (row, column)
   T* out = Vp + q * (int64_t)K * W;
   for (int i = tid; i < K * W; i += 256) {
-    const int h = i & 1, jo = (i >> 1) & 1, li = (i >> 2) & 63, blk = i >> 8;
-    const int r = blk % R, jp = blk / R;
-    const int row = 4 * (2 * jp + jo) + (li >> 4);
-    const int col = 32 * r + 16 * h + (li & 15);
+    int row, col;
+    if constexpr (NK == 2) {
+      const int h = i & 1, jo = (i >> 1) & 1, li = (i >> 2) & 63, blk = i >> 8;
+      const int r = blk % R, jp = blk / R;
+      row = 4 * (2 * jp + jo) + (li >> 4);
+      col = 32 * r + 16 * h + (li & 15);
+    } else {
+      const int jj = i & 3, li = (i >> 2) & 63, jq = i >> 8;
+      row = 4 * (4 * jq + jj) + (li >> 4);
+      col = li & 15;
+    }
     const int p = point_of_row<PA>(row, NAB);
     out[i] = p >= 0 ? acc[p][col] : (T)0;
   }
@@ -640,24 +703,25 @@ __global__ void __launch_bounds__(256) k_prop_mfma(DevLevel C, DevLevel P, Inter
 // interpolation onto cousin targets: two threads per target, one per
 // wavenumber q (the 16 columns of a cone row split 8 + 8 by kernel); each
 // loops over the target's cousin cones.  blockIdx.y selects the right-hand
-// side r of the batch of R.
-template <int PS, int PA, class T, int R>
+// side r of the batch of R.  NK = 1 (one kernel per pass): one thread per
+// target for kernel k0, whose 14 sums go to outputs 14 qo .. 14 qo + 13.
+template <int PS, int PA, class T, int R, int NK>
 __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const double* __restrict__ xs,
                             const double* __restrict__ nrm, int64_t n, double k0, double k1,
-                            const T* __restrict__ V, double2* __restrict__ out_s) {
+                            const T* __restrict__ V, double2* __restrict__ out_s, int qo) {
   constexpr int NAB = KSlot<PS, PA>::NAB;
   constexpr int TC = KSlot<PS, PA>::TC;
-  constexpr int K = KSlot<PS, PA>::K;
+  constexpr int K = NK == 2 ? KSlot<PS, PA>::K : KSlot<PS, PA>::K1;
   const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t i = g >> 1;
-  const int q = (int)(g & 1);
+  const int64_t i = NK == 2 ? g >> 1 : g;
+  const int q = NK == 2 ? (int)(g & 1) : 0;
   if (i >= n) return;
   const int64_t e0 = L.tp_off[i], e1 = L.tp_off[i + 1];
   if (e0 == e1) return;
   const T nx = (T)nrm[3 * i], ny = (T)nrm[3 * i + 1], nz = (T)nrm[3 * i + 2];
   const T kq = (T)(q == 0 ? k0 : k1);
   const int rr = blockIdx.y;
-  double2* o = out_s + ((int64_t)rr * n + i) * 28 + q * 14;
+  double2* o = out_s + ((int64_t)rr * n + i) * 28 + (NK == 2 ? q : qo) * 14;
   T Sr[8], Si[8], Dr[6], Di[6];
 #pragma unroll
   for (int m = 0; m < 8; ++m) { Sr[m] = (T)0; Si[m] = (T)0; }
@@ -698,7 +762,7 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
     for (int m = 0; m < 16; ++m) F[m] = (T)0;
 #pragma unroll
     for (int m = 0; m < 12; ++m) FD[m] = (T)0;
-    const T* Vs = V + (int64_t)slot * K * 32 * R;
+    const T* Vs = V + (int64_t)slot * K * row_reals(R, NK);
     // radial index a runs in a rolled loop; Ls/dLs rotate so indices stay static
 #pragma unroll 1
     for (int a = 0; a < PS; ++a) {
@@ -730,17 +794,19 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
             Lp[PA - 1] = l0;
             dLp[PA - 1] = d0;
           }
-          // column 8 q + m: real part at vr[4 m], imaginary part at vr[4 m + 1]
-          const T* vr = Vs + kofs<R>(row, 32 * rr + 8 * q);
+          // NK = 2: column 8 q + m, real part at vr[4 m], imaginary part at
+          // vr[4 m + 1]; NK = 1: real part at vr[4 m], imaginary at vr[4 (8 + m)]
+          const T* vr = Vs + (NK == 2 ? kofs<R>(row, 32 * rr + 8 * q) : kofs1(row, 0));
+          constexpr int IM = NK == 2 ? 1 : 32;
 #pragma unroll
           for (int m = 0; m < 8; ++m) {
             F[m] += w * vr[4 * m];
-            F[8 + m] += w * vr[4 * m + 1];
+            F[8 + m] += w * vr[4 * m + IM];
           }
 #pragma unroll
           for (int m = 0; m < 6; ++m) {
             FD[m] += wd * vr[4 * m];
-            FD[6 + m] += wd * vr[4 * m + 1];
+            FD[6 + m] += wd * vr[4 * m + IM];
           }
         }
       }
@@ -789,7 +855,9 @@ __global__ void __launch_bounds__(64) k_targets_k(DevLevel L, InterpC ic, const 
 // the interpolation weights at x + h n in the cone of x (extrapolating where
 // x + h n leaves it), and the normal derivative is (G(x + h n, x_B)
 // F(x + h n) - G(x, x_B) F(x)) / h, h = 1e-6.
-template <int PS, int PA, class T, bool FD, int R>
+// NK = 1 (one kernel per pass): the 8 columns of kernel k0 only; a pair's
+// 14 contributions go to res[(e R + r) 28].
+template <int PS, int PA, class T, bool FD, int R, int NK>
 __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, TargetTiles TT,
                                                       const double* __restrict__ xs,
                                                       const double* __restrict__ nrm, double k0, double k1,
@@ -797,7 +865,8 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   constexpr int NAB = KSlot<PS, PA>::NAB;
   constexpr int TC = KSlot<PS, PA>::TC;
   constexpr int KS = KSlot<PS, PA>::KS;
-  constexpr int K = KSlot<PS, PA>::K;
+  constexpr int K = NK == 2 ? KSlot<PS, PA>::K : KSlot<PS, PA>::K1;
+  constexpr int WR = row_reals(R, NK);   // reals per cone row
   // per-target record: Ls, c_s dLs, Lt, c_t dLt, Lp, c_ph dLp, then
   // Re G_q, Im G_q (q = 0, 1), -n.r-hat / r, n.r-hat; with FD the derivative
   // slots hold Ls, Lt, Lp at x + h n and Re G_q, Im G_q there follow
@@ -854,7 +923,7 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
         lag<PA, T>(Nodes<T>::xa(ic), Nodes<T>::wa(ic), up2, dLp);
         c_s = c_t = c_ph = (T)1;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NK; ++q) {
           T sn, cs;
           tsincos<T>((T)(q == 0 ? k0 : k1) * r2, &sn, &cs);
           o[OG + 6 + q] = cs * (T)kInv4PiD / r2;
@@ -874,7 +943,7 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
         o[OPD + z] = c_ph * dLp[z];
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NK; ++q) {
         T sn, cs;
         tsincos<T>((T)(q == 0 ? k0 : k1) * r, &sn, &cs);
         o[OG + q] = cs * (T)kInv4PiD * rinv;
@@ -928,12 +997,14 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
 #pragma unroll
   for (int r = 0; r < R; ++r) c0[r] = c1[r] = typename MF<T>::acc{0, 0, 0, 0};
   // R right-hand sides: each cone row holds R groups of 32 values, pair jp
-  // of right-hand side r at (jp R + r) 256 reals (MFMA consumption order)
-  const T* Vs = V + (int64_t)slot * K * 32 * R + 4 * lane;
-  // B operands of a pair of k-steps are requested PD - 1 pairs ahead of
-  // their use (see the propagation kernel)
+  // of right-hand side r at (jp R + r) 256 reals (MFMA consumption order);
+  // NK = 1: quad jp of k-steps at jp 256 reals
+  const T* Vs = V + (int64_t)slot * K * WR + 4 * lane;
+  // B operands of a pair (quad) of k-steps are requested PD - 1 loads ahead
+  // of their use (see the propagation kernel)
   using V4 = typename Vec4<T>::type;
-  constexpr int NP = KSlot<PS, PA>::KS2 / 2;
+  constexpr int SPL = NK == 2 ? 2 : 4;  // k-steps per load
+  constexpr int NP = NK == 2 ? KSlot<PS, PA>::KS2 / 2 : KSlot<PS, PA>::KS4 / 4;
   constexpr int PD = prop_prefetch(sizeof(T));
   V4 ring[PD][R];
 #pragma unroll
@@ -942,8 +1013,8 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
     for (int r = 0; r < R; ++r) ring[i][r] = *reinterpret_cast<const V4*>(Vs + (int64_t)(i * R + r) * 256);
 #pragma unroll
   for (int j = 0; j < KS; ++j) {
-    const int jp = j >> 1;
-    if ((j & 1) == 0 && jp + PD - 1 < NP)
+    const int jp = j / SPL;
+    if (j % SPL == 0 && jp + PD - 1 < NP)
 #pragma unroll
       for (int r = 0; r < R; ++r)
         ring[(jp + PD - 1) % PD][r] = *reinterpret_cast<const V4*>(Vs + (int64_t)((jp + PD - 1) * R + r) * 256);
@@ -965,15 +1036,20 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const V4& b4 = ring[jp % PD][r];
-      c0[r] = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0[r]);
-      c1[r] = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1[r]);
+      if constexpr (NK == 2) {
+        c0[r] = MF<T>::mma(av, (j & 1) ? b4[2] : b4[0], c0[r]);
+        c1[r] = MF<T>::mma(av, (j & 1) ? b4[3] : b4[1], c1[r]);
+      } else {
+        c0[r] = MF<T>::mma(av, b4[j & 3], c0[r]);
+      }
     }
-    if (j & 1) __builtin_amdgcn_sched_barrier(0);
+    if (j % SPL == SPL - 1) __builtin_amdgcn_sched_barrier(0);
   }
   T(*ob)[33] = outb[wave];
   // epilogue, one right-hand side at a time through the wavefront's LDS
   // buffer: lane -> target lane / 8, density m = lane % 8, both kernels;
-  // results of right-hand side r at res[(e R + r) 56]
+  // results of right-hand side r at res[(e R + r) 56] (NK = 1: column m of
+  // ob holds the real, column 8 + m the imaginary part; res[(e R + r) 28])
   const int tt = lane >> 3, m = lane & 7;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -986,7 +1062,7 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
     for (int e = 0; e < 4; ++e) {
       const int row = MF<T>::row(lane, e);
       ob[row][r16] = c0[r][e];
-      ob[row][16 + r16] = c1[r][e];
+      if constexpr (NK == 2) ob[row][16 + r16] = c1[r][e];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -994,16 +1070,16 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   if (tt < cnt) {
     const int64_t e = TT.e[kbeg + tt];
     const T* g = rw[tt] + OG;
-    T* out = res + (e * R + r) * 56;
+    T* out = res + (e * R + r) * 28 * NK;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int col = 8 * q + m;
-      const T fr = ob[2 * tt][col], fi = ob[2 * tt][16 + col];
+    for (int q = 0; q < NK; ++q) {
+      const int col = 8 * q + m, cim = NK == 2 ? 16 + col : 8 + m;
+      const T fr = ob[2 * tt][col], fi = ob[2 * tt][cim];
       const T gr = g[q], gi = g[2 + q];
       out[2 * (14 * q + m)] = gr * fr - gi * fi;
       out[2 * (14 * q + m) + 1] = gr * fi + gi * fr;
       if (m < 6) {
-        const T dr = ob[2 * tt + 1][col], di = ob[2 * tt + 1][16 + col];
+        const T dr = ob[2 * tt + 1][col], di = ob[2 * tt + 1][cim];
         if constexpr (FD) {
           const T g2r = g[6 + q], g2i = g[8 + q];
           const T ih = (T)(1.0 / kFdH);
@@ -1021,77 +1097,78 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   }
 }
 
-// out_s[r][i][k] += sum over the target pairs e of i of res[(e - e0) R + r][k],
-// k < 28, for targets i0 <= i < i1 whose pairs start at e0 = tp_off[i0] and
-// right-hand sides r < R (FP64 sums; out_s holds n points per right-hand side)
+// out_s[r][i][ko + k] += sum over the target pairs e of i of
+// res[(e - e0) R + r][k], k < nk (28, or the 14 of one kernel), for targets
+// i0 <= i < i1 whose pairs start at e0 = tp_off[i0] and right-hand sides r < R
+// (FP64 sums; out_s holds n points of 28 outputs per right-hand side)
 template <class T>
 __global__ void __launch_bounds__(256) k_targets_reduce(const int64_t* __restrict__ tp_off, int64_t n, int64_t i0,
-                                                        int64_t i1, int R, const T* __restrict__ res,
+                                                        int64_t i1, int R, int nk, int ko, const T* __restrict__ res,
                                                         double2* __restrict__ out_s) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (i1 - i0) * 28;
+  const int64_t per = (i1 - i0) * nk;
   if (g >= per * R) return;
   const int r = (int)(g / per);
-  const int64_t i = i0 + (g % per) / 28;
-  const int k = (int)(g % 28);
+  const int64_t i = i0 + (g % per) / nk;
+  const int k = (int)(g % nk);
   const int64_t e0 = tp_off[i0];
   double re = 0.0, im = 0.0;
   for (int64_t e = tp_off[i] - e0; e < tp_off[i + 1] - e0; ++e) {
-    re += (double)res[(e * R + r) * 56 + 2 * k];
-    im += (double)res[(e * R + r) * 56 + 2 * k + 1];
+    re += (double)res[(e * R + r) * 2 * nk + 2 * k];
+    im += (double)res[(e * R + r) * 2 * nk + 2 * k + 1];
   }
-  const int64_t o = (int64_t)r * 28 * n + i * 28 + k;
+  const int64_t o = (int64_t)r * 28 * n + i * 28 + ko + k;
   const double2 v = out_s[o];
   out_s[o] = make_double2(v.x + re, v.y + im);
 }
 
 inline unsigned nblk(int64_t w, int bs) { return (unsigned)((w + bs - 1) / bs); }
 
-template <int PS, int PA, class T, int R>
+template <int PS, int PA, class T, int R, int NK>
 hipError_t leaf_t(const DevLevel& L, const InterpC& ic, const double* xs, const void* a, double k0,
                   double k1, void* V, hipStream_t st) {
-  constexpr int K = KSlot<PS, PA>::K;
+  constexpr int K = NK == 2 ? KSlot<PS, PA>::K : KSlot<PS, PA>::K1;
   int64_t work = L.nslots * K * R;
   if (work <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_leaf_k<PS, PA, T, R>), dim3(nblk(work, 256)), dim3(256), 0, st, L, ic, xs,
+  hipLaunchKernelGGL((k_leaf_k<PS, PA, T, R, NK>), dim3(nblk(work, 256)), dim3(256), 0, st, L, ic, xs,
                      static_cast<const T*>(a), k0, k1, static_cast<T*>(V));
   return hipGetLastError();
 }
-template <int PS, int PA, class T, int R>
+template <int PS, int PA, class T, int R, int NK>
 hipError_t prop_t(const DevLevel& C, const DevLevel& P, const InterpC& ic, const PropGroups& G,
                   double k0, double k1, const void* Vc, void* Vp, int spin_limit, unsigned* err,
                   hipStream_t st) {
-  if constexpr (prop_lds_bytes(PS, PA, R, sizeof(T)) > kLdsLimit) {
+  if constexpr (prop_lds_bytes(PS, PA, row_reals(R, NK), sizeof(T)) > kLdsLimit) {
     return hipErrorInvalidValue;   // excluded by max_batch_columns
   } else {
     if (P.nslots <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_prop_mfma<PS, PA, T, R>), dim3((unsigned)P.nslots), dim3(256), 0, st, C, P, ic, G, k0,
+    hipLaunchKernelGGL((k_prop_mfma<PS, PA, T, R, NK>), dim3((unsigned)P.nslots), dim3(256), 0, st, C, P, ic, G, k0,
                        k1, static_cast<const T*>(Vc), static_cast<T*>(Vp), spin_limit, err);
     return hipGetLastError();
   }
 }
-template <int PS, int PA, class T, int R>
+template <int PS, int PA, class T, int R, int NK>
 hipError_t targets_t(const DevLevel& L, const InterpC& ic, const double* xs, const double* nrm,
-                     int64_t n, double k0, double k1, const void* V, double2* out_s, hipStream_t st) {
+                     int64_t n, double k0, double k1, const void* V, double2* out_s, int qo, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_targets_k<PS, PA, T, R>), dim3(nblk(2 * n, 64), R), dim3(64), 0, st, L, ic, xs, nrm, n, k0,
-                     k1, static_cast<const T*>(V), out_s);
+  hipLaunchKernelGGL((k_targets_k<PS, PA, T, R, NK>), dim3(nblk(NK * n, 64), R), dim3(64), 0, st, L, ic, xs, nrm, n,
+                     k0, k1, static_cast<const T*>(V), out_s, qo);
   return hipGetLastError();
 }
-template <int PS, int PA, class T, int R>
+template <int PS, int PA, class T, int R, int NK>
 hipError_t targets_tiles_t(const DevLevel& L, const InterpC& ic, const TargetTiles& TT, const double* xs,
                            const double* nrm, double k0, double k1, const void* V, void* res, bool fd,
                            hipStream_t st) {
   if (TT.ntiles <= 0) return hipSuccess;
   if (fd) {
     if constexpr (std::is_same<T, double>::value && R == 1)
-      hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, true, 1>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic,
-                         TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+      hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, true, 1, NK>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L,
+                         ic, TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
     else
       return hipErrorInvalidValue;   // the forward difference is FP64 with one right-hand side only
   } else {
-    hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, false, R>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L, ic,
-                       TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
+    hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, false, R, NK>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L,
+                       ic, TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
   }
   return hipGetLastError();
 }
@@ -1118,54 +1195,59 @@ hipError_t with_orders(int Ps, int Pa, F&& f) {
   return hipErrorInvalidValue;
 }
 
-// R = 1, 2 or 4 right-hand sides per pass; FP64 takes at most 2 (the LDS of
-// the propagation at R = 4 would exceed a workgroup's 160 KB)
+// R = 1, 2 or 4 right-hand sides per pass with both kernels (NK = 2); FP64
+// takes at most 2 (the LDS of the propagation at R = 4 would exceed a
+// workgroup's 160 KB).  One kernel per pass (NK = 1) takes R = 1 only.
 template <class T, class F>
-hipError_t with_columns(int R, F&& f) {
+hipError_t with_columns(int R, int nk, F&& f) {
+  if (nk == 1) return R == 1 ? f.template operator()<1, 1>() : hipErrorInvalidValue;
+  if (nk != 2) return hipErrorInvalidValue;
   switch (R) {
-    case 1: return f.template operator()<1>();
-    case 2: return f.template operator()<2>();
+    case 1: return f.template operator()<1, 2>();
+    case 2: return f.template operator()<2, 2>();
     case 4:
-      if constexpr (std::is_same<T, float>::value) return f.template operator()<4>();
+      if constexpr (std::is_same<T, float>::value) return f.template operator()<4, 2>();
       break;
   }
   return hipErrorInvalidValue;
 }
 
 template <class T>
-hipError_t dispatch_leaf(int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t dispatch_leaf(int Ps, int Pa, int R, int nk, const DevLevel& L, const InterpC& ic, const double* xs,
                          const void* a, double k0, double k1, void* V, hipStream_t st) {
   return with_orders(Ps, Pa, [&]<int PS, int PA>() {
-    return with_columns<T>(R, [&]<int RR>() { return leaf_t<PS, PA, T, RR>(L, ic, xs, a, k0, k1, V, st); });
+    return with_columns<T>(R, nk, [&]<int RR, int NK>() {
+      return leaf_t<PS, PA, T, RR, NK>(L, ic, xs, a, k0, k1, V, st);
+    });
   });
 }
 template <class T>
-hipError_t dispatch_prop(int Ps, int Pa, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
+hipError_t dispatch_prop(int Ps, int Pa, int R, int nk, const DevLevel& C, const DevLevel& P, const InterpC& ic,
                          const PropGroups& G, double k0, double k1, const void* Vc, void* Vp, int spin_limit,
                          unsigned* err, hipStream_t st) {
   return with_orders(Ps, Pa, [&]<int PS, int PA>() {
-    return with_columns<T>(R, [&]<int RR>() {
-      return prop_t<PS, PA, T, RR>(C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st);
+    return with_columns<T>(R, nk, [&]<int RR, int NK>() {
+      return prop_t<PS, PA, T, RR, NK>(C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st);
     });
   });
 }
 template <class T>
-hipError_t dispatch_targets(int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
+hipError_t dispatch_targets(int Ps, int Pa, int R, int nk, const DevLevel& L, const InterpC& ic, const double* xs,
                             const double* nrm, int64_t n, double k0, double k1, const void* V,
-                            double2* out_s, hipStream_t st) {
+                            double2* out_s, int qo, hipStream_t st) {
   return with_orders(Ps, Pa, [&]<int PS, int PA>() {
-    return with_columns<T>(R, [&]<int RR>() {
-      return targets_t<PS, PA, T, RR>(L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+    return with_columns<T>(R, nk, [&]<int RR, int NK>() {
+      return targets_t<PS, PA, T, RR, NK>(L, ic, xs, nrm, n, k0, k1, V, out_s, qo, st);
     });
   });
 }
 template <class T>
-hipError_t dispatch_targets_tiles(int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic,
+hipError_t dispatch_targets_tiles(int Ps, int Pa, int R, int nk, const DevLevel& L, const InterpC& ic,
                                   const TargetTiles& TT, const double* xs, const double* nrm, double k0, double k1,
                                   const void* V, void* res, bool fd, hipStream_t st) {
   return with_orders(Ps, Pa, [&]<int PS, int PA>() {
-    return with_columns<T>(R, [&]<int RR>() {
-      return targets_tiles_t<PS, PA, T, RR>(L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
+    return with_columns<T>(R, nk, [&]<int RR, int NK>() {
+      return targets_tiles_t<PS, PA, T, RR, NK>(L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
     });
   });
 }
@@ -1174,15 +1256,15 @@ hipError_t dispatch_targets_tiles(int Ps, int Pa, int R, const DevLevel& L, cons
 
 bool mfma_path_supported(int Ps, int Pa) { return (Pa == 5 || Pa == 6) && Ps >= 3 && Ps <= 6; }
 
-int kslot_rows(int Ps, int Pa) {
+int kslot_rows(int Ps, int Pa, int nk) {
   const int nab = Pa * Ps, tc = Pa - 4;
   const int ks = nab + (tc * nab + 3) / 4;
-  return 4 * (ks + (ks & 1));
+  return nk == 1 ? 4 * ((ks + 3) & ~3) : 4 * (ks + (ks & 1));
 }
 
 int max_batch_columns(bool fp32, int Ps, int Pa) {
   for (int R = fp32 ? 4 : 2; R > 1; R /= 2)
-    if (prop_lds_bytes(Ps, Pa, R, fp32 ? 4 : 8) <= kLdsLimit) return R;
+    if (prop_lds_bytes(Ps, Pa, row_reals(R, 2), fp32 ? 4 : 8) <= kLdsLimit) return R;
   return 1;
 }
 
@@ -1198,42 +1280,44 @@ hipError_t mf_gather(bool fp32, int R, const double2* dens, const int64_t* perm,
   return hipGetLastError();
 }
 
-hipError_t mf_leaf(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
-                   const void* a, double k0, double k1, void* V, hipStream_t st) {
-  return fp32 ? dispatch_leaf<float>(Ps, Pa, R, L, ic, xs, a, k0, k1, V, st)
-              : dispatch_leaf<double>(Ps, Pa, R, L, ic, xs, a, k0, k1, V, st);
+hipError_t mf_leaf(bool fp32, int Ps, int Pa, int R, int nk, const DevLevel& L, const InterpC& ic,
+                   const double* xs, const void* a, double k0, double k1, void* V, hipStream_t st) {
+  return fp32 ? dispatch_leaf<float>(Ps, Pa, R, nk, L, ic, xs, a, k0, k1, V, st)
+              : dispatch_leaf<double>(Ps, Pa, R, nk, L, ic, xs, a, k0, k1, V, st);
 }
 
-hipError_t mf_propagate(bool fp32, int Ps, int Pa, int R, const DevLevel& C, const DevLevel& P, const InterpC& ic,
-                        const PropGroups& G, double k0, double k1, const void* Vc, void* Vp, int spin_limit,
-                        unsigned* err, hipStream_t st) {
-  return fp32 ? dispatch_prop<float>(Ps, Pa, R, C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st)
-              : dispatch_prop<double>(Ps, Pa, R, C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st);
+hipError_t mf_propagate(bool fp32, int Ps, int Pa, int R, int nk, const DevLevel& C, const DevLevel& P,
+                        const InterpC& ic, const PropGroups& G, double k0, double k1, const void* Vc, void* Vp,
+                        int spin_limit, unsigned* err, hipStream_t st) {
+  return fp32 ? dispatch_prop<float>(Ps, Pa, R, nk, C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st)
+              : dispatch_prop<double>(Ps, Pa, R, nk, C, P, ic, G, k0, k1, Vc, Vp, spin_limit, err, st);
 }
 
-hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic, const double* xs,
-                      const double* nrm, int64_t n, double k0, double k1, const void* V,
-                      double2* out_s, hipStream_t st) {
-  return fp32 ? dispatch_targets<float>(Ps, Pa, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st)
-              : dispatch_targets<double>(Ps, Pa, R, L, ic, xs, nrm, n, k0, k1, V, out_s, st);
+hipError_t mf_targets(bool fp32, int Ps, int Pa, int R, int nk, const DevLevel& L, const InterpC& ic,
+                      const double* xs, const double* nrm, int64_t n, double k0, double k1, const void* V,
+                      double2* out_s, int qo, hipStream_t st) {
+  return fp32 ? dispatch_targets<float>(Ps, Pa, R, nk, L, ic, xs, nrm, n, k0, k1, V, out_s, qo, st)
+              : dispatch_targets<double>(Ps, Pa, R, nk, L, ic, xs, nrm, n, k0, k1, V, out_s, qo, st);
 }
 
-hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, int R, const DevLevel& L, const InterpC& ic,
+hipError_t mf_targets_tiles(bool fp32, int Ps, int Pa, int R, int nk, const DevLevel& L, const InterpC& ic,
                             const TargetTiles& TT, const double* xs, const double* nrm, double k0, double k1,
                             const void* V, void* res, bool fd, hipStream_t st) {
-  return fp32 ? dispatch_targets_tiles<float>(Ps, Pa, R, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st)
-              : dispatch_targets_tiles<double>(Ps, Pa, R, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
+  return fp32 ? dispatch_targets_tiles<float>(Ps, Pa, R, nk, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st)
+              : dispatch_targets_tiles<double>(Ps, Pa, R, nk, L, ic, TT, xs, nrm, k0, k1, V, res, fd, st);
 }
 
-hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int R, int64_t n, int64_t i0, int64_t i1, const void* res,
-                             double2* out_s, hipStream_t st) {
+hipError_t mf_targets_reduce(bool fp32, const DevLevel& L, int R, int nk, int qo, int64_t n, int64_t i0, int64_t i1,
+                             const void* res, double2* out_s, hipStream_t st) {
   if (i1 <= i0) return hipSuccess;
-  const unsigned nb = nblk((i1 - i0) * 28 * R, 256);
+  if (nk != 1 && nk != 2) return hipErrorInvalidValue;
+  const int w = 14 * nk, ko = nk == 1 ? 14 * qo : 0;
+  const unsigned nb = nblk((i1 - i0) * w * R, 256);
   if (fp32)
-    hipLaunchKernelGGL(k_targets_reduce<float>, dim3(nb), dim3(256), 0, st, L.tp_off, n, i0, i1, R,
+    hipLaunchKernelGGL(k_targets_reduce<float>, dim3(nb), dim3(256), 0, st, L.tp_off, n, i0, i1, R, w, ko,
                        static_cast<const float*>(res), out_s);
   else
-    hipLaunchKernelGGL(k_targets_reduce<double>, dim3(nb), dim3(256), 0, st, L.tp_off, n, i0, i1, R,
+    hipLaunchKernelGGL(k_targets_reduce<double>, dim3(nb), dim3(256), 0, st, L.tp_off, n, i0, i1, R, w, ko,
                        static_cast<const double*>(res), out_s);
   return hipGetLastError();
 }

@@ -164,3 +164,37 @@ def test_plan_refuses_more_cones_per_box_than_32_bit_indices_hold():
     n = np.tile([0.0, 0.0, 1.0], (50, 1))
     with pytest.raises(binding.IFGFError, match="2\\^31 cones"):
         binding.ifgf_plan(x, n, np.ones(50), 2 * math.pi, 2 * math.pi, 1e-3, host_only=1)
+
+
+@pytest.mark.parametrize("orders", [(4, 6), (4, 5), (3, 5)])
+def test_one_kernel_per_pass_halves_the_cone_buffers(orders):
+    """Remark 3: the interpolation data of one kernel at a time take half the
+    memory of both kernels' (up to the padding of a cone's k-steps to a
+    multiple of 4 instead of 2), computed from the relevant cone counts
+    before any device memory is touched."""
+    s = synth.cube_sphere(2, 8)
+    Ps, Pa = orders
+    h = binding.ifgf_plan(s.x, s.normal, np.ones(s.n), 3 * math.pi, 2 * math.pi, 1e-3,
+                          Ps=Ps, Pa=Pa, host_only=1, plan_on_device=0)
+    try:
+        st = binding.ifgf_stats(h)
+        both, one = st["cone_buffer_bytes_by_mode"]
+        D = st["D"]
+        slots = [max([L["slots"] for L in st["levels"] if (D - L["d"]) % 2 == b] or [0]) for b in (0, 1)]
+        nab = Ps * Pa
+        ks = nab + ((Pa - 4) * nab + 3) // 4
+        rows_both, rows_one = 4 * (ks + ks % 2), 4 * ((ks + 3) // 4 * 4)
+        assert both == sum(8 * max(sl, 1) * rows_both * 32 for sl in slots)
+        assert one == sum(8 * max(sl, 1) * rows_one * 16 for sl in slots)
+        assert one * 2 * rows_both == both * rows_one
+        assert st["kernels_per_pass"] == 0          # host-only plans hold no buffers
+    finally:
+        binding.ifgf_destroy(h)
+
+
+@pytest.mark.parametrize("kw,msg", [(dict(kernel_at_a_time=2), "kernel_at_a_time"),
+                                    (dict(cone_memory_budget=-1), "cone_memory_budget")])
+def test_plan_rejects_bad_kernel_mode_options(kw, msg):
+    s = synth.cube_sphere(1, 4)
+    with pytest.raises(binding.IFGFError, match=msg):
+        binding.ifgf_plan(s.x, s.normal, np.ones(s.n), 3.0, 2.0, 1e-3, host_only=1, **kw)
