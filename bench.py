@@ -400,7 +400,8 @@ def waveguide(args, log):
     ke = omega * math.sqrt(eps_e)
     free0 = torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
-    op = NMullerOperator(surf, eps_e, eps_i, tol=args.tol, precision=B.IFGF_FP32, fp32_workspaces=1, verbose=1)
+    op = NMullerOperator(surf, eps_e, eps_i, tol=args.tol, precision=B.IFGF_FP32, fp32_workspaces=1, verbose=1,
+                         kernel_at_a_time=1 if args.wg_one_kernel else 0)
     plan_s = time.perf_counter() - t0
     free1 = torch.cuda.mem_get_info()[0]
     info = op.plan_info()
@@ -452,7 +453,7 @@ def waveguide(args, log):
     nq = 100
     dims = [8 * nq + 4, 256, 256, 8 * nq]
     op.set_preconditioner(np.zeros(sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(3)), np.float32), dims)
-    restart = 80
+    restart = args.wg_restart
     ysol = torch.zeros_like(b)
     iters, t_gm, cycles, last = 0, 0.0, 0, None
     while iters < args.maxit:
@@ -489,6 +490,7 @@ def waveguide(args, log):
                       "correction_pairs": info["correction_pairs"],
                       "correction_GiB": round(info["correction_bytes"] / 2**30, 2),
                       "ifgf_cone_buffer_GiB": round(st0.get("cone_buffer_bytes", 0) / 2**30, 2),
+                      "ifgf_kernels_per_pass": st0.get("kernels_per_pass"),
                       "ifgf_target_result_GiB": round(st0.get("target_result_bytes", 0) / 2**30, 2),
                       "plan_device_GiB": round((free0 - free1) / 2**30, 2),
                       "peak_device_GiB": round(peak_gib, 2)},
@@ -578,6 +580,9 @@ def main():
     ap.add_argument("--waveguide", action="store_true",
                     help="the 1.67M-point rounded-box waveguide workload instead (N-Mueller matvecs and "
                          "GMRES with the dipole excitation; ~10 minutes)")
+    ap.add_argument("--wg-one-kernel", action="store_true",
+                    help="waveguide: one kernel per IFGF pass (half the cone buffers, room for a larger Krylov basis)")
+    ap.add_argument("--wg-restart", type=int, default=80, help="waveguide: FGMRES restart length")
     ap.add_argument("--no-kat", action="store_true",
                     help="skip the one-kernel-per-pass (Remark 3) measurement")
     ap.add_argument("--no-bodies32", action="store_true",

@@ -73,7 +73,8 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  *   device memory of the default, which keeps room for the FP64 form); such a
  *   plan cannot be switched to IFGF_FP64 (ifgf_set_precision: IFGF_EINVAL).
  * verbose: 1 prints one progress line per planning stage and level on
- *   stderr (large surfaces take minutes to plan).
+ *   stderr (large surfaces take minutes to plan), and one line per 20
+ *   iterations of the solves on an N-Mueller operator built with it.
  * deriv_mode: how the normal derivative of a cousin contribution is taken
  *   (Sec. III-I): IFGF_DERIV_ANALYTIC (default) differentiates the
  *   interpolant times the centred factor; IFGF_DERIV_FD is the paper's

@@ -114,6 +114,7 @@ void timer_end(ifgf_plan_s* p, const char* name, hipEvent_t ev, hipStream_t st, 
   if (p) p->timer.end(name, ev, st, units);
 }
 bool timing_on(ifgf_plan_s* p) { return p && p->timer.on; }
+bool plan_verbose(ifgf_plan_s* p) { return p && p->opt.verbose; }
 }  // namespace ifgf
 
 namespace {

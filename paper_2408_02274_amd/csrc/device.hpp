@@ -65,4 +65,5 @@ namespace ifgf {
 hipEvent_t timer_begin(ifgf_plan_s* p, hipStream_t st);
 void timer_end(ifgf_plan_s* p, const char* name, hipEvent_t ev, hipStream_t st, double units);
 bool timing_on(ifgf_plan_s* p);   // per-kernel timing switched on
+bool plan_verbose(ifgf_plan_s* p);   // built with the verbose option
 }  // namespace ifgf

@@ -21,6 +21,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <algorithm>
 #include <complex>
 #include <memory>
@@ -28,6 +29,7 @@
 #include <vector>
 
 #include "../../include/ifgf.h"
+#include "device.hpp"
 #include "precond.hpp"
 #include "util.hpp"
 
@@ -241,6 +243,7 @@ class Fgmres {
         hv_(S.basis + 2) {
     pc_ = precond ? nmuller_precond(S.nm) : nullptr;
     net_ = pc_ != nullptr;
+    verbose_ = plan_verbose(nmuller_ifgf(S.nm));
   }
 
   int start(Req* req, bool* done) {
@@ -364,6 +367,7 @@ class Fgmres {
     ++total_;
     if (flex_ && net_) ++pc_iters_;
     hist_.push_back(est_);
+    if (verbose_ && total_ % 20 == 0) std::fprintf(stderr, "[gmres] %d iterations, residual estimate %.3e\n", total_, est_);
     if (rec_ && rec_->count < rec_->cap && total_ % rec_->stride == 0 && (rc = record())) return rc;
     if (est_ <= rtol_ || hn == 0.0) return end_cycle(req, done);
     if (flex_ && net_ && k_ >= kStallWindow && !(est_ < kStallRatio * hist_[k_ - kStallWindow])) {
@@ -443,6 +447,7 @@ class Fgmres {
   int basis_;
   std::vector<cd> H_, cs_, sn_, g_, hv_;
   std::vector<double> hist_;
+  bool verbose_ = false;
   double bnorm_ = 0.0, est_ = 0.0, truerel_ = 0.0;
   int total_ = 0, pc_iters_ = 0, fallbacks_ = 0, k_ = 0;
   bool flex_ = false, abandon_ = false;

@@ -99,7 +99,9 @@ __global__ void __launch_bounds__(256) k_pre(GeoDev g, const double2* __restrict
   }
 }
 
-// a7: out += C phi for the singular patches of every target (one wavefront per target)
+// a7: out += C phi for the singular patches of every target (one wavefront per
+// target).  The lanes run over the (patch, node) pairs of the target's rows
+// as one flat range, so every lane has work in every step but the last.
 __global__ void __launch_bounds__(256) k_correct(const int64_t* __restrict__ row_off, const int32_t* __restrict__ pair_patch,
                           const double2* __restrict__ vals, int nq, int64_t n,
                           const double2* __restrict__ phi, double2* __restrict__ out, int nrhs) {
@@ -111,21 +113,31 @@ __global__ void __launch_bounds__(256) k_correct(const int64_t* __restrict__ row
   double2 acc[28];
 #pragma unroll
   for (int k = 0; k < 28; ++k) acc[k] = make_double2(0.0, 0.0);
-  for (int64_t e = row_off[l]; e < row_off[l + 1]; ++e) {
-    const int64_t base = (int64_t)pair_patch[e] * nq;
-    const double2* C = vals + e * 4 * nq;
-    for (int q = lane; q < nq; q += 64) {
+  const int64_t e0 = row_off[l];
+  const int tot = (int)(row_off[l + 1] - e0) * nq;
+  // flat index f = pair * nq + node, advanced by 64 per step
+  int el = lane / nq, q = lane - (lane / nq) * nq;
+  for (int f = lane; f < tot; f += 64) {
+    {
+      const int64_t e = e0 + el;
+      const int64_t base = (int64_t)pair_patch[e] * nq;
+      const double2* C = vals + e * 4 * nq;
       double2 w0 = C[q], w1 = C[nq + q], w2 = C[2 * nq + q], w3 = C[3 * nq + q];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        double2 f = ph[c * n + base + q];
-        acc[c] = cadd(acc[c], cmulc(w0, f));            // S, k_int
-        acc[14 + c] = cadd(acc[14 + c], cmulc(w1, f));  // S, k_ext
+        double2 v = ph[c * n + base + q];
+        acc[c] = cadd(acc[c], cmulc(w0, v));            // S, k_int
+        acc[14 + c] = cadd(acc[14 + c], cmulc(w1, v));  // S, k_ext
         if (c < 6) {
-          acc[8 + c] = cadd(acc[8 + c], cmulc(w2, f));    // D, k_int
-          acc[22 + c] = cadd(acc[22 + c], cmulc(w3, f));  // D, k_ext
+          acc[8 + c] = cadd(acc[8 + c], cmulc(w2, v));    // D, k_int
+          acc[22 + c] = cadd(acc[22 + c], cmulc(w3, v));  // D, k_ext
         }
       }
+    }
+    q += 64;
+    while (q >= nq) {
+      q -= nq;
+      ++el;
     }
   }
 #pragma unroll
