@@ -41,14 +41,17 @@ TRAFFIC = os.path.join(ROOT, "profiles", "propagate_fp32_sphere153k_hbm_traffic.
 KERNEL_SRC = os.path.join(ROOT, "paper_2408_02274_amd", "csrc", "ifgf_mfma.hip")
 
 
-def flops_per_unit(name, npts):
+def flops_per_unit(name, npts, nk=2):
     """Algorithmic flops per work unit (FMA = 2 flops, transcendental = 1,
-    real x complex multiply-add = 4)."""
+    real x complex multiply-add = 4) of one IFGF pass carrying nk kernels:
+    2 (both, 16 complex columns) or 1 (one kernel per pass, 8 columns; the
+    pass repeats the geometry)."""
+    c = 8 * nk
     return {
         "near": 280.0,                                   # (target, source) pair, 2 wavenumbers
-        "leaf": 160.0,                                   # (interpolation point, source) pair
-        "targets": 4.0 * npts * 16 + 4.0 * npts * 12 + 10.0 * npts + 300.0,   # (target, cousin box)
-        "propagate": 4.0 * npts * 16 + 2.0 * npts + 150.0,                    # (parent point, child box)
+        "leaf": 160.0 if nk == 2 else 90.0,              # (interpolation point, source) pair
+        "targets": 4.0 * npts * c + 4.0 * npts * 6 * nk + 10.0 * npts + 300.0,   # (target, cousin box)
+        "propagate": 4.0 * npts * c + 2.0 * npts + 150.0,                       # (parent point, child box)
         "nm_correct": 224.0,                             # (target, singular-patch node) pair
     }.get(name, 0.0)
 
@@ -544,9 +547,10 @@ def waveguide(args, log):
 
 def kernel_table(st, steps, npts):
     kern = {}
+    nk = st.get("kernels_per_pass") or 2
     for name, t in st.get("timing", {}).items():
         kern[name] = {"launches": t["launches"], "ms": t["ms"],
-                      "flop": flops_per_unit(name, npts) * t["units"],
+                      "flop": flops_per_unit(name, npts, nk) * t["units"],
                       "bytes": bytes_per_unit(name) * t["units"]}
     return kern
 

@@ -27,6 +27,17 @@ def test_per_unit_flops_at_orders_4_6():
     assert bench.flops_per_unit("targets", npts) == 17868.0
 
 
+def test_per_unit_flops_of_one_kernel_per_pass():
+    npts = 4 * 6 * 6
+    # a pass carries 8 complex columns; its geometry and epilogue terms stay
+    assert bench.flops_per_unit("propagate", npts, nk=1) == 4 * npts * 8 + 2 * npts + 150 == 5046.0
+    assert bench.flops_per_unit("targets", npts, nk=1) == 4 * npts * 8 + 4 * npts * 6 + 10 * npts + 300 == 9804.0
+    st = {"kernels_per_pass": 1, "timing": {"propagate": {"launches": 8, "ms": 2.0, "units": 10.0}}}
+    assert bench.kernel_table(st, 1, npts)["propagate"]["flop"] == 50460.0
+    st["kernels_per_pass"] = 0          # host-only plans report 0: both kernels
+    assert bench.kernel_table(st, 1, npts)["propagate"]["flop"] == 96540.0
+
+
 def test_per_unit_flops_at_orders_5_5():
     npts = 5 * 5 * 5
     # (parent point, child box) pair: 16 complex columns x npts real weights, centring, geometry
