@@ -236,6 +236,8 @@ constexpr int64_t prop_lds_bytes(int Ps, int Pa, int W, int elem) {
   return prop_lds_bytes_tb(Ps, Pa, W, elem, prop_tiles_per_batch(Ps, Pa, W, elem));
 }
 constexpr int64_t kLdsLimit = 160 * 1024;
+// tiles of the target interpolation whose records a wavefront computes together
+constexpr int target_tiles_per_wave(int elem) { return elem == 4 ? 4 : 2; }
 // pairs of k-steps whose B operands a propagation wavefront keeps in flight
 // (FP64 operands take twice the registers)
 constexpr int prop_prefetch(int elem) { return elem == 4 ? 6 : 3; }
@@ -873,22 +875,27 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   constexpr int OLS = 0, OSD = PS, OLT = 2 * PS, OTD = 2 * PS + PA, OLP = 2 * PS + 2 * PA,
                 OPD = 2 * PS + 3 * PA, OG = 2 * PS + 4 * PA, TW = OG + (FD ? 10 : 6);
   constexpr double kFdH = 1e-6;
-  __shared__ T rec[4][8][TW];
+  // A wavefront takes TBT consecutive tiles: all their target records are
+  // computed at once, lane l for target l mod 8 of tile l / 8, then the
+  // tiles run on the matrix cores one after the other.
+  constexpr int TBT = target_tiles_per_wave(sizeof(T));
+  __shared__ T rec[4][8 * TBT][TW];
   __shared__ T outb[4][16][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, gl = lane >> 4;
-  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (tile >= TT.ntiles) return;   // whole wavefront; only wavefront barriers follow
-  const int32_t slot = TT.slot[tile];
-  const int64_t kbeg = TT.start[tile];
-  const int cnt = TT.cnt[tile];
-  const int cone = L.slot_cone[slot];
-  const double* c = L.centers + 3 * L.slot_box[slot];
+  const int64_t tile0 = (xcd_remap(blockIdx.x, gridDim.x) * 4 + wave) * TBT;
+  if (tile0 >= TT.ntiles) return;   // whole wavefront; only wavefront barriers follow
+  const int nt = (int)(TT.ntiles - tile0 < TBT ? TT.ntiles - tile0 : TBT);
   T(*rw)[TW] = rec[wave];
-  if (lane < 8) {
+  if (lane < 8 * TBT) {
     T* o = rw[lane];
-    if (lane < cnt) {
-      const int64_t i = TT.tgt[kbeg + lane];
+    const int tl = lane >> 3, k = lane & 7;
+    const int cntl = tl < nt ? (int)TT.cnt[tile0 + tl] : 0;
+    if (k < cntl) {
+      const int32_t slot = TT.slot[tile0 + tl];
+      const int cone = L.slot_cone[slot];
+      const double* c = L.centers + 3 * L.slot_box[slot];
+      const int64_t i = TT.tgt[TT.start[tile0 + tl] + k];
       const T nx = (T)nrm[3 * i], ny = (T)nrm[3 * i + 1], nz = (T)nrm[3 * i + 2];
       const T zx = (T)(xs[3 * i] - c[0]), zy = (T)(xs[3 * i + 1] - c[1]), zz = (T)(xs[3 * i + 2] - c[2]);
       T r, us, ut, up, th, ph;
@@ -958,13 +965,25 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+  for (int ti = 0; ti < nt; ++ti) {
+  const int64_t tile = tile0 + ti;
+  const int32_t slot = TT.slot[tile];
+  const int64_t kbeg = TT.start[tile];
+  const int cnt = TT.cnt[tile];
+  if (ti > 0) {
+    // the epilogue of the tile before has read the output buffer
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   // A operand of row r16 (target t, value or derivative) at node (a, b, c):
   //   value:      Ls[a] Lt[b] Lp[c]
   //   derivative: (c_s dLs[a]) Lt[b] Lp[c] + Ls[a] (c_t dLt[b]) Lp[c] + Ls[a] Lt[b] (c_ph dLp[c])
   // = Lt[b] U[a] + (c_t dLt[b]) W[a] with per-lane U, W for the phi-node c
   const int t = r16 >> 1;
   const T kv = (r16 & 1) ? (T)0 : (T)1, kd = (T)1 - kv;
-  const T* me = rw[t];
+  const T* me = rw[8 * ti + t];
   // (FD: value rows Lt[b] U[a], U = Ls Lp; difference rows Lt2[b] W[a], W = Ls2 Lp2)
   T U[PS], W[PS], Ltv[PA], Tdv[PA];
   if constexpr (FD) {
@@ -1069,7 +1088,7 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (tt < cnt) {
     const int64_t e = TT.e[kbeg + tt];
-    const T* g = rw[tt] + OG;
+    const T* g = rw[8 * ti + tt] + OG;
     T* out = res + (e * R + r) * 28 * NK;
 #pragma unroll
     for (int q = 0; q < NK; ++q) {
@@ -1093,6 +1112,7 @@ __global__ void __launch_bounds__(256) k_targets_mfma(DevLevel L, InterpC ic, Ta
         }
       }
     }
+  }
   }
   }
 }
@@ -1162,12 +1182,12 @@ hipError_t targets_tiles_t(const DevLevel& L, const InterpC& ic, const TargetTil
   if (TT.ntiles <= 0) return hipSuccess;
   if (fd) {
     if constexpr (std::is_same<T, double>::value && R == 1)
-      hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, true, 1, NK>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L,
+      hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, true, 1, NK>), dim3(nblk(TT.ntiles, 4 * target_tiles_per_wave(sizeof(T)))), dim3(256), 0, st, L,
                          ic, TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
     else
       return hipErrorInvalidValue;   // the forward difference is FP64 with one right-hand side only
   } else {
-    hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, false, R, NK>), dim3(nblk(TT.ntiles, 4)), dim3(256), 0, st, L,
+    hipLaunchKernelGGL((k_targets_mfma<PS, PA, T, false, R, NK>), dim3(nblk(TT.ntiles, 4 * target_tiles_per_wave(sizeof(T)))), dim3(256), 0, st, L,
                        ic, TT, xs, nrm, k0, k1, static_cast<const T*>(V), static_cast<T*>(res));
   }
   return hipGetLastError();
