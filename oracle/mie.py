@@ -7,7 +7,7 @@ and a sphere of radius a centred at the origin with wavenumbers k (outside)
 and k1 (inside), mu = mu1 = 1.  The paper compares its solver with this
 series on the unit sphere (Sec. IV-B).
 
-Pins (tests/test_oracle_mie.py): the incident expansion reproduces the plane
+Pins (tests/test_oracle_nmuller.py, test_mie_series_self_consistent): the incident expansion reproduces the plane
 wave, tangential E and H are continuous across r = a, and the small-sphere
 (Rayleigh) limit of the interior field is the uniform 3/(eps_r + 2) E_inc.
 """
