@@ -272,6 +272,20 @@ __global__ void k_gather(const double2* __restrict__ dens, const int64_t* __rest
   a[2 * t + 1] = (T)(v.y * w[i]);
 }
 
+// sin and cos of a leaf phase k (|X - y| - |X - c|), and the divisions of the
+// leaf geometry.  The phase is below a quarter turn at the leaf level (boxes
+// of at most a quarter wavelength), where the FP32 form takes the hardware
+// sine and cosine (argument in revolutions) and a reciprocal-based divide;
+// the FP64 form keeps the library functions.
+template <class T> __device__ __forceinline__ void leaf_sincos(T x, T* s, T* c) { tsincos<T>(x, s, c); }
+template <> __device__ __forceinline__ void leaf_sincos<float>(float x, float* s, float* c) {
+  const float rev = x * (float)(0.5 / kPiD);
+  *s = __builtin_amdgcn_sinf(rev);
+  *c = __builtin_amdgcn_cosf(rev);
+}
+template <class T> __device__ __forceinline__ T leaf_div(T a, T b) { return a / b; }
+template <> __device__ __forceinline__ float leaf_div<float>(float a, float b) { return __fdividef(a, b); }
+
 // leaf cone values: thread per (slot, row, right-hand side).  NK = 1: the
 // 8 columns of kernel k0 only (one kernel per pass).
 template <int PS, int PA, class T, int R, int NK>
@@ -315,13 +329,13 @@ __global__ void __launch_bounds__(256) k_leaf_k(DevLevel L, InterpC ic, const do
     const T yx = (T)(xs[3 * j] - c[0]), yy = (T)(xs[3 * j + 1] - c[1]), yz = (T)(xs[3 * j + 2] - c[2]);
     const T dx = Yx - yx, dy = Yy - yy, dz = Yz - yz;
     const T rxy = tsqrt<T>(dx * dx + dy * dy + dz * dz);
-    const T diff = (yx * yx + yy * yy + yz * yz - (T)2 * (Yx * yx + Yy * yy + Yz * yz)) / (rxy + rxc);
-    const T ratio = rxc / rxy;
+    const T diff = leaf_div<T>(yx * yx + yy * yy + yz * yz - (T)2 * (Yx * yx + Yy * yy + Yz * yz), rxy + rxc);
+    const T ratio = leaf_div<T>(rxc, rxy);
     const T* aj = a + ((int64_t)j * R + r) * 16;
 #pragma unroll
     for (int qq = 0; qq < NK; ++qq) {
       T sn, cs;
-      tsincos<T>(kk[qq] * diff, &sn, &cs);
+      leaf_sincos<T>(kk[qq] * diff, &sn, &cs);
       const T gr = ratio * cs, gi = ratio * sn;
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
