@@ -103,7 +103,11 @@ typedef struct ifgf_plan_s* ifgf_plan_t;
  * cone_memory_budget: bytes the cone buffers may take when
  *   kernel_at_a_time = -1; 0 = the free device memory at plan time less the
  *   plan's other workspaces (a caller that allocates more afterwards, such
- *   as the N-Mueller corrections, passes its own budget).                  */
+ *   as the N-Mueller corrections, passes its own budget).
+ * target_tiles: 1 (default) interpolates onto the cousin targets on the
+ *   matrix cores, in cone-major tiles of up to 8 targets; 0 uses one thread
+ *   per (target, kernel) instead (slower; the same sums up to rounding;
+ *   IFGF_DERIV_FD needs the tiles).                                        */
 typedef struct {
   int Ps, Pa;
   int ns_init, na_init;
@@ -121,6 +125,7 @@ typedef struct {
   int keep_pair_tables;
   int kernel_at_a_time;
   int64_t cone_memory_budget;
+  int target_tiles;
 } ifgf_options;
 
 void ifgf_default_options(ifgf_options* opt);

@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("batch_columns", C.c_int), ("fp32_workspaces", C.c_int), ("verbose", C.c_int),
                 ("deriv_mode", C.c_int), ("target_chunk_pairs", C.c_int64), ("plan_on_device", C.c_int),
                 ("keep_pair_tables", C.c_int), ("kernel_at_a_time", C.c_int),
-                ("cone_memory_budget", C.c_int64)]
+                ("cone_memory_budget", C.c_int64), ("target_tiles", C.c_int)]
 
 
 class NMullerParams(C.Structure):

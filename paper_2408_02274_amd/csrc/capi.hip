@@ -244,6 +244,7 @@ void ifgf_default_options(ifgf_options* opt) {
   opt->keep_pair_tables = 0;
   opt->kernel_at_a_time = 0;
   opt->cone_memory_budget = 0;
+  opt->target_tiles = 1;
 }
 
 int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* normals,
@@ -399,7 +400,7 @@ int ifgf_plan(ifgf_plan_t* out, int64_t n, const double* points, const double* n
     std::vector<int32_t>().swap(L.pg_cbox);
     std::vector<int32_t>().swap(L.pg_count);
     std::vector<uint8_t>().swap(L.pg_pts);
-    if (p->mfma && d >= 3 && !L.tt_slot.empty()) {
+    if (p->mfma && d >= 3 && !L.tt_slot.empty() && opt.target_tiles) {
       TargetTiles& TT = p->ttiles[d];
       int32_t *sl = nullptr, *tg = nullptr, *ee = nullptr;
       int64_t* stt = nullptr;

@@ -334,3 +334,31 @@ def test_forward_difference_derivative_matches_reference(order):
         assert _rel(g[q, 8:], ga[q, 8:]) < 1e-3
     with pytest.raises(B.IFGFError):
         _gpu_apply(s.x, s.normal, w, ks, phi, Ps=Ps, Pa=Pa, deriv_mode=B.IFGF_DERIV_FD, precision=B.IFGF_FP32)
+
+
+@pytest.mark.parametrize("prec,kat,nrhs", [(0, 0, 1), (0, 1, 1), (1, 0, 2), (1, 1, 1)])
+def test_per_target_interpolation_equals_the_matrix_core_tiles(prec, kat, nrhs):
+    """target_tiles = 0 interpolates onto the cousin targets with one thread
+    per (target, kernel) instead of the matrix-core tiles: the same sums, for
+    both kernels per pass and one kernel per pass, and with two right-hand
+    sides per pass.  Bars: 1e-12 in FP64; 1e-5 in FP32, where the two paths
+    sum the 144 interpolation terms of a cone in different orders (one
+    thread in sequence against the MFMA's k-groups), each rounding at about
+    sqrt(144) x 6e-8 relative before the centred factor (measured 1.2e-6)."""
+    from paper_2408_02274_amd import IFGFPlan
+    s, ks = CASES["ellipsoid"]()
+    w = np.random.default_rng(8).uniform(0.5, 1.5, s.n)
+    phi = synth.complex_normal((nrhs, 8, s.n), 9)
+    _say(f"[gpu] per-target interpolation vs tiles: precision {prec}, kernel_at_a_time {kat}, nrhs {nrhs}")
+    out = []
+    for tiles in (1, 0):
+        plan = IFGFPlan(s.x, s.normal, w, ks[0], ks[1], 1e-4, precision=prec, kernel_at_a_time=kat,
+                        max_nrhs=nrhs, batch_columns=nrhs, target_tiles=tiles)
+        paths = {L["target_path"] for L in plan.stats()["levels"]}
+        assert ("mfma_tiles" in paths) if tiles else (paths == {"per_target"})
+        out.append(plan.apply(torch.from_numpy(phi).to("cuda")).cpu().numpy())
+        plan.close()
+    assert _rel(out[1], out[0]) < (1e-12 if prec == 0 else 1e-5)
+    if prec == 0 and kat == 1:
+        o2 = ifgf_ref.ReferenceIFGF(s.x, s.normal, w, ks, ifgf_ref.Params(Ps=4, Pa=6, refine_radial=True)).apply(phi[0])
+        assert _rel(out[1][0], o2) < 1e-10
